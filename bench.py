@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark of the non-separable 2-D lifting DWT on one MI355X.
+
+Headline workload: CDF 9/7 forward transform, one level, of one 8192 x 8192
+FP32 image (pixels uniform in [0, 1), seed 0), whole-point symmetric borders.
+A step is one dwt2_fwd call on that image; inputs are resident in HBM before
+the timed region, and three input/output pairs are rotated so that the 256 MB
+Infinity Cache cannot serve a step from the previous step's data.
+
+Printed: one JSON line with the contract fields, a `roofline` object for the
+level kernel (algorithmic bytes: each pixel read once, each coefficient
+written once = 2 * 4 B/px) and a `cpu_baseline` object (the CPU oracle timed
+on a bounded crop of the same image).  `forms` lists the other forms of the
+path (5 levels, BF16 / FP16 storage, the P0/P1 split, inverse, reversible
+5/3) on the same image size, measured the same way with fewer steps.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=8192)
+    ap.add_argument("--no-forms", action="store_true", help="skip the secondary forms")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def algorithmic_bytes(h, w, levels, elem):
+    """Compulsory traffic: every level reads its input once and writes its
+    h x w outputs once."""
+    total = 0
+    for _ in range(levels):
+        total += 2 * h * w * elem
+        h, w = (h + 1) // 2, (w + 1) // 2
+    return total
+
+
+def time_steps(torch, fn, steps, warmup):
+    """Run warmup untimed steps, then time `steps` steps.  Returns (total ms
+    between synchronisations, per-step event durations in ms)."""
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record(stream)
+        fn(i)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    total_ms = (time.perf_counter() - t0) * 1e3
+    per = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return total_ms, per
+
+
+def cpu_baseline(x, seconds):
+    """The CPU oracle (FP64 NumPy separable lifting, one core) on a 2048 x 2048
+    crop of the benchmark image, repeated for about `seconds`."""
+    from oracle import lifting
+    crop = x[:2048, :2048]
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        lifting.fwd(crop, "cdf97", 1)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    gpx = n * crop.size / el / 1e9
+    return {"value": gpx, "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} x CDF 9/7 fwd 1 level on the 2048x2048 top-left crop of the same "
+                      f"image, FP64 NumPy, single thread, {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(this build has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1704_08657_amd as d
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    N = args.size
+    x_host = workloads.uniform(N, N, seed=0)
+    pairs = 3
+    xs = [torch.from_numpy(x_host).to(dev)]
+    for k in range(1, pairs):
+        xs.append(xs[0].roll(k, dims=1).contiguous())
+    ys = [torch.empty_like(xs[0]) for _ in range(pairs)]
+    torch.cuda.synchronize()
+
+    def fwd_step(i):
+        d.fwd(xs[i % pairs], "cdf97", 1, out=ys[i % pairs])
+
+    total_ms, per = time_steps(torch, fwd_step, args.steps, args.warmup)
+    ms_step = total_ms / args.steps
+    px = N * N
+    value = px / (ms_step * 1e-3) / 1e9
+    kern_ms = float(np.mean(per))
+    abytes = algorithmic_bytes(N, N, 1, 4)
+    achieved = abytes / (kern_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "level_kernel<fwd, cdf97, f32>", "algorithmic_bytes_per_launch": abytes,
+                "avg_launch_ms": round(kern_ms, 5), "median_launch_ms": round(float(np.median(per)), 5)}
+
+    forms = []
+    if not args.no_forms:
+        def form(name, fn, levels, elem, steps=50):
+            tot, pr = time_steps(torch, fn, steps, 5)
+            ms = float(np.median(pr))
+            ab = algorithmic_bytes(N, N, levels, elem)
+            forms.append({"form": name, "Gpixel/s": round(px / (ms * 1e-3) / 1e9, 2),
+                          "ms": round(ms, 4), "GB/s": round(ab / (ms * 1e-3) / 1e9, 1),
+                          "hbm_frac": round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+
+        ws5 = d.workspace(N, N, 5, d.DWT2_F32, dev)
+        form("cdf97 fwd f32 5 levels", lambda i: d.fwd(xs[i % pairs], "cdf97", 5, out=ys[i % pairs]), 5, 4)
+        form("cdf97 fwd f32 1 level split P0/P1",
+             lambda i: d.fwd(xs[i % pairs], "cdf97", 1, split=True, out=ys[i % pairs]), 1, 4)
+        form("cdf97 inv f32 1 level", lambda i: d.inv(ys[i % pairs], "cdf97", 1, out=xs[i % pairs]), 1, 4)
+        del ws5
+        for tdt, nm in [(torch.bfloat16, "bf16"), (torch.float16, "f16")]:
+            xb = [t.to(tdt) for t in xs]
+            yb = [torch.empty_like(t) for t in xb]
+            form(f"cdf97 fwd {nm} 1 level", lambda i: d.fwd(xb[i % pairs], "cdf97", 1, out=yb[i % pairs]), 1, 2)
+            form(f"cdf97 fwd {nm} 5 levels", lambda i: d.fwd(xb[i % pairs], "cdf97", 5, out=yb[i % pairs]), 5, 2)
+            del xb, yb
+        xi = [(t * 255).to(torch.int32) for t in xs]
+        yi = [torch.empty_like(t) for t in xi]
+        form("cdf53 fwd i32 1 level", lambda i: d.fwd(xi[i % pairs], "cdf53", 1, out=yi[i % pairs]), 1, 4)
+        form("cdf53 inv i32 1 level", lambda i: d.inv(yi[i % pairs], "cdf53", 1, out=xi[i % pairs]), 1, 4)
+        del xi, yi
+
+    cpu = None if args.no_cpu else cpu_baseline(x_host, args.cpu_seconds)
+
+    line = {
+        "metric": "Gpixel/s 2-D CDF 9/7 fwd 8192^2 FP32 (+ % HBM roofline)",
+        "value": round(value, 2),
+        "unit": "Gpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"CDF 9/7 forward, 1 level, one {N}x{N} FP32 image, uniform [0,1) seed 0, "
+                               "whole-point symmetric borders, non-separable lifting (4 barriers)",
+                   "height": N, "width": N, "levels": 1, "rotating_buffers": pairs},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "forms": forms,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,153 @@
+/*
+ * dwt2.h -- C ABI of a 2-D discrete wavelet transform for AMD Instinct MI355X
+ * (gfx950), computed with the non-separable lifting scheme of Barina, Kula,
+ * Matysek and Zemcik, "Accelerating Discrete Wavelet Transforms on Parallel
+ * Architectures" (WSCG 2017).
+ *
+ * What is computed (Section "Background"): one scale splits an image into the
+ * quadruple of polyphase components x0 = X[2n][2m], x1 = X[2n][2m+1],
+ * x2 = X[2n+1][2m], x3 = X[2n+1][2m+1] and maps them by K pairs of lifting
+ * steps, eq. (2).  The kernels apply each pair as the two fused spatial steps
+ * of Section "Proposed Schemes",
+ *     T_P : x1 += P x0, x2 += P* x0, x3 += P P* x0 + P* x1 + P x2
+ *     S_U : x0 += U x1 + U* x2 + U U* x3, x1 += U* x3, x2 += U x3
+ * with one work-group barrier per step.  With DWT2_FLAG_SPLIT the constant
+ * parts P0, U0 run as barrier-free separable lifting and only P1, U1 stay in
+ * the fused step (Section "Optimization Approach").
+ *
+ * Conventions (the paper leaves them open; the library fixes them):
+ *   - Output layout: Mallat pyramid in an H x W array.  Level l transforms the
+ *     LL of level l-1 (ceil halving).  For a level of size h x w with
+ *     he = ceil(h/2), we = ceil(w/2): LL = [0,he) x [0,we), HL (x1, high
+ *     horizontally) = [0,he) x [we,w), LH (x2) = [he,h) x [0,we),
+ *     HH (x3) = [he,h) x [we,w).
+ *   - Borders: whole-point symmetric extension (X[-k] = X[k],
+ *     X[N-1+k] = X[N-1-k]) per axis, the only boundary supported.
+ *   - CDF 9/7: Daubechies-Sweldens lifting constants, then LL * zeta^2,
+ *     HH * zeta^-2 (HL, LH unscaled), zeta = 1.1496043988602418, so that a
+ *     constant image c gives LL = 2c per level.  Arithmetic is FP32 for every
+ *     storage type; BF16/FP16 values are rounded to nearest-even on every
+ *     store (intermediate LL levels included).
+ *   - Reversible CDF 5/3 (int32 only): odd -= floor((e[m] + e[m+1]) / 2),
+ *     even += floor((o[m-1] + o[m] + 2) / 4), in the order T^H, T^V, S^H, S^V
+ *     of the separable scheme; exact integer arithmetic.  Pixels must satisfy
+ *     |x| < 2^28 (not checked on the device).
+ *
+ * Memory and streams: every pointer is a device pointer owned by the caller.
+ * The library never allocates, frees or synchronises on these calls; all work
+ * is enqueued on `stream` (a hipStream_t; NULL is the default stream) and the
+ * call returns once it is enqueued.  src and dst must not overlap; the
+ * workspace must not overlap either.  Pitches are in elements.
+ *
+ * Errors: every argument check runs on the host before any HIP call; on an
+ * error the call returns a negative dwt2_status, enqueues nothing and leaves
+ * dst untouched.  DWT2_E_HIP reports a HIP runtime error at launch; its text
+ * is returned by dwt2_last_hip_error() (thread-local).
+ */
+#ifndef DWT2_H
+#define DWT2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DWT2_OK = 0,
+    DWT2_E_NULL = -1,       /* a required pointer is NULL                       */
+    DWT2_E_SHAPE = -2,      /* height or width < 2 (or > 2^30)                  */
+    DWT2_E_LEVELS = -3,     /* levels < 1 or > dwt2_max_levels(height, width)   */
+    DWT2_E_DTYPE = -4,      /* unknown dtype, or dtype not valid for wavelet    */
+    DWT2_E_WAVELET = -5,    /* unknown wavelet                                  */
+    DWT2_E_BOUNDARY = -6,   /* unknown boundary extension                       */
+    DWT2_E_PITCH = -7,      /* pitch < width                                    */
+    DWT2_E_WORKSPACE = -8,  /* workspace NULL or smaller than required          */
+    DWT2_E_ALIAS = -9,      /* src, dst or workspace overlap                    */
+    DWT2_E_HIP = -10,       /* HIP runtime error at launch                      */
+    DWT2_E_FLAGS = -11,     /* unknown flag, or flag not valid for the wavelet  */
+    DWT2_E_COUNT = -12      /* batched call: count < 1                          */
+} dwt2_status;
+
+typedef enum {
+    DWT2_CDF97 = 0,         /* CDF 9/7, float storage (F32, BF16, F16)          */
+    DWT2_CDF53_REV = 1      /* reversible integer CDF 5/3, I32 storage only     */
+} dwt2_wavelet;
+
+typedef enum {
+    DWT2_F32 = 0,
+    DWT2_BF16 = 1,
+    DWT2_F16 = 2,
+    DWT2_I32 = 3
+} dwt2_dtype;
+
+typedef enum {
+    DWT2_SYMMETRIC_WHOLE = 0
+} dwt2_boundary;
+
+/* Flags (bitwise or). */
+#define DWT2_FLAG_SPLIT 1u   /* P = P0 + P1, U = U0 + U1 operation-count reduction
+                                (Section "Optimization Approach"); CDF 9/7 only.
+                                Same values up to FP32 rounding.               */
+
+/* One image of a batched call.  Pitches in elements. */
+typedef struct {
+    const void* src;
+    void* dst;
+    int32_t height;
+    int32_t width;
+    int64_t src_pitch;
+    int64_t dst_pitch;
+} dwt2_image;
+
+/* Largest level count for which every transformed level is at least 2 x 2;
+ * 0 if height or width < 2. */
+int dwt2_max_levels(int32_t height, int32_t width);
+
+/* Device workspace (bytes) that dwt2_fwd / dwt2_inv / dwt2_adj need for this
+ * shape, level count and storage type: two ping-pong buffers for the
+ * intermediate LL bands (0 for one level).  Returns a dwt2_status. */
+int dwt2_workspace_bytes(int32_t height, int32_t width, int levels,
+                         dwt2_dtype dtype, size_t* bytes);
+
+/* Forward transform (Section "Proposed Schemes", non-separable lifting):
+ * src = image (height x width, src_pitch), dst = Mallat pyramid
+ * (height x width, dst_pitch).  Multi-level: levels >= 1. */
+int dwt2_fwd(const void* src, void* dst, int32_t height, int32_t width,
+             int64_t src_pitch, int64_t dst_pitch, dwt2_dtype dtype,
+             dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,
+             unsigned flags, void* workspace, size_t workspace_bytes,
+             void* stream);
+
+/* Inverse transform: src = Mallat pyramid, dst = image.  Each fused step is
+ * undone in reverse order (S_{-U} then T_{-P} per pair; for the integer 5/3
+ * the vertical half of each step is undone before the horizontal half). */
+int dwt2_inv(const void* src, void* dst, int32_t height, int32_t width,
+             int64_t src_pitch, int64_t dst_pitch, dwt2_dtype dtype,
+             dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,
+             unsigned flags, void* workspace, size_t workspace_bytes,
+             void* stream);
+
+/* Adjoint (transpose) of dwt2_fwd: src = cotangent in Mallat layout, dst =
+ * W^T src in image layout.  The transposed fused steps run in reverse order,
+ * coarsest level first; at the borders the transposes of the symmetric
+ * extension are used (they are not a symmetric extension).  CDF 9/7 only;
+ * flags must be 0. */
+int dwt2_adj(const void* src, void* dst, int32_t height, int32_t width,
+             int64_t src_pitch, int64_t dst_pitch, dwt2_dtype dtype,
+             dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,
+             unsigned flags, void* workspace, size_t workspace_bytes,
+             void* stream);
+
+/* Text of a dwt2_status. */
+const char* dwt2_status_string(int status);
+
+/* Text of the last HIP error reported as DWT2_E_HIP on this thread. */
+const char* dwt2_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DWT2_H */

@@ -1,0 +1,218 @@
+"""Python binding of libdwt2: the non-separable 2-D lifting DWT on MI355X.
+
+The library (C ABI in include/dwt2.h) computes the transform of Barina et
+al., "Accelerating Discrete Wavelet Transforms on Parallel Architectures":
+each pair of separable lifting steps fused into one spatial predict T_P and
+one spatial update S_U per barrier, CDF 9/7 (FP32 arithmetic; FP32, BF16 or
+FP16 storage) and reversible CDF 5/3 (int32), forward, inverse and adjoint,
+multi-level Mallat layout, whole-point symmetric borders.
+
+This module only marshals arguments: PyTorch supplies device memory and the
+current stream; every step of the transform runs in the HIP kernels.  There
+is no CPU fallback: if the library is not built or the tensor is not on a
+GPU, the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdwt2.so")
+
+# enums of include/dwt2.h
+DWT2_OK = 0
+DWT2_E_HIP = -10
+DWT2_CDF97, DWT2_CDF53_REV = 0, 1
+DWT2_F32, DWT2_BF16, DWT2_F16, DWT2_I32 = 0, 1, 2, 3
+DWT2_SYMMETRIC_WHOLE = 0
+DWT2_FLAG_SPLIT = 1
+
+WAVELETS = {"cdf97": DWT2_CDF97, "cdf53": DWT2_CDF53_REV}
+
+# every function the header declares, with its ctypes signature
+_c_int, _c_i32, _c_i64, _c_u, _c_sz, _c_p = (ctypes.c_int, ctypes.c_int32, ctypes.c_int64,
+                                             ctypes.c_uint, ctypes.c_size_t, ctypes.c_void_p)
+_TRANSFORM_ARGS = [_c_p, _c_p, _c_i32, _c_i32, _c_i64, _c_i64, _c_int, _c_int, _c_int, _c_int,
+                   _c_u, _c_p, _c_sz, _c_p]
+SIGNATURES = {
+    "dwt2_max_levels": (_c_int, [_c_i32, _c_i32]),
+    "dwt2_workspace_bytes": (_c_int, [_c_i32, _c_i32, _c_int, _c_int, ctypes.POINTER(_c_sz)]),
+    "dwt2_fwd": (_c_int, _TRANSFORM_ARGS),
+    "dwt2_inv": (_c_int, _TRANSFORM_ARGS),
+    "dwt2_adj": (_c_int, _TRANSFORM_ARGS),
+    "dwt2_status_string": (ctypes.c_char_p, [_c_int]),
+    "dwt2_last_hip_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class DWT2Error(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = f"{what}: {status_string(status)} ({status})"
+        if status == DWT2_E_HIP:
+            msg += ": " + lib().dwt2_last_hip_error().decode()
+        super().__init__(msg)
+        self.status = status
+
+
+def lib():
+    """The loaded libdwt2.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1704_08657_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+# ---- thin wrappers with the C names -------------------------------------
+
+def dwt2_max_levels(height: int, width: int) -> int:
+    return lib().dwt2_max_levels(height, width)
+
+
+def dwt2_workspace_bytes(height: int, width: int, levels: int, dtype: int):
+    """(status, bytes)."""
+    n = ctypes.c_size_t(0)
+    st = lib().dwt2_workspace_bytes(height, width, levels, dtype, ctypes.byref(n))
+    return st, n.value
+
+
+def dwt2_fwd(*args) -> int:
+    return lib().dwt2_fwd(*args)
+
+
+def dwt2_inv(*args) -> int:
+    return lib().dwt2_inv(*args)
+
+
+def dwt2_adj(*args) -> int:
+    return lib().dwt2_adj(*args)
+
+
+def status_string(status: int) -> str:
+    return lib().dwt2_status_string(status).decode()
+
+
+# ---- tensor-level API -----------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def dtype_code(t) -> int:
+    torch = _torch()
+    codes = {torch.float32: DWT2_F32, torch.bfloat16: DWT2_BF16,
+             torch.float16: DWT2_F16, torch.int32: DWT2_I32}
+    if t.dtype not in codes:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return codes[t.dtype]
+
+
+def _check(x):
+    if not x.is_cuda:
+        raise RuntimeError("dwt2 runs on the GPU only: move the tensor to a HIP device")
+    if x.dim() < 2:
+        raise ValueError("expected a tensor [..., H, W]")
+    if x.stride(-1) != 1:
+        raise ValueError("the last dimension must be contiguous")
+
+
+def _stream_ptr(x):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
+
+
+def workspace(h: int, w: int, levels: int, dtype, device):
+    """A workspace tensor for one call on an h x w image (None if not needed)."""
+    torch = _torch()
+    st, n = dwt2_workspace_bytes(h, w, levels, dtype)
+    if st != DWT2_OK:
+        raise DWT2Error(st, "dwt2_workspace_bytes")
+    if n == 0:
+        return None
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def _transform(fn, name, x, wavelet, levels, split, out):
+    torch = _torch()
+    _check(x)
+    x2 = x.reshape(-1, *x.shape[-2:]) if x.is_contiguous() else x.contiguous().reshape(-1, *x.shape[-2:])
+    if out is None:
+        out = torch.empty_like(x2)
+    else:
+        _check(out)
+        if out.shape != x.shape or out.dtype != x.dtype:
+            raise ValueError("out must match the input's shape and dtype")
+        out = out.reshape(x2.shape)
+    H, W = x2.shape[-2:]
+    dt = dtype_code(x2)
+    ws = workspace(H, W, levels, dt, x2.device)
+    ws_ptr = ctypes.c_void_p(ws.data_ptr() if ws is not None else 0)
+    ws_n = ws.numel() if ws is not None else 0
+    stream = _stream_ptr(x2)
+    flags = DWT2_FLAG_SPLIT if split else 0
+    for i in range(x2.shape[0]):
+        st = fn(ctypes.c_void_p(x2[i].data_ptr()), ctypes.c_void_p(out[i].data_ptr()), H, W,
+                x2.stride(-2), out.stride(-2), dt, WAVELETS[wavelet], levels,
+                DWT2_SYMMETRIC_WHOLE, flags, ws_ptr, ws_n, stream)
+        if st != DWT2_OK:
+            raise DWT2Error(st, name)
+    return out.reshape(x.shape)
+
+
+def fwd(x, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None):
+    """Forward transform of every [H, W] plane of x into a Mallat pyramid."""
+    return _transform(dwt2_fwd, "dwt2_fwd", x, wavelet, levels, split, out)
+
+
+def inv(c, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None):
+    """Inverse transform of every [H, W] Mallat pyramid of c."""
+    return _transform(dwt2_inv, "dwt2_inv", c, wavelet, levels, split, out)
+
+
+def adj(g, levels: int = 1, out=None):
+    """Adjoint W^T g of the CDF 9/7 forward transform (cotangent in Mallat layout)."""
+    return _transform(dwt2_adj, "dwt2_adj", g, "cdf97", levels, False, out)
+
+
+def _make_function():
+    torch = _torch()
+
+    class DWT2Function(torch.autograd.Function):
+        """Forward CDF 9/7 transform whose backward is the hand-written adjoint."""
+
+        @staticmethod
+        def forward(ctx, x, levels: int = 1):
+            ctx.levels = levels
+            return fwd(x.contiguous(), "cdf97", levels)
+
+        @staticmethod
+        def backward(ctx, g):
+            return adj(g.contiguous(), ctx.levels), None
+
+    return DWT2Function
+
+
+_fn_cls = None
+
+
+def DWT2Function():
+    """The torch.autograd.Function class (created on first use)."""
+    global _fn_cls
+    if _fn_cls is None:
+        _fn_cls = _make_function()
+    return _fn_cls
+
+
+def dwt2(x, levels: int = 1):
+    """Differentiable forward CDF 9/7 transform of x [..., H, W] (FP32)."""
+    return DWT2Function().apply(x, levels)

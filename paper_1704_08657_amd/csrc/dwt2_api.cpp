@@ -1,0 +1,282 @@
+// C ABI of the 2-D lifting DWT library: argument checks, level planning,
+// workspace layout and kernel dispatch.  Every check runs on the host before
+// the first HIP call, so an invalid call enqueues nothing.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/dwt2.h"
+#include "dwt2_internal.h"
+
+namespace {
+
+thread_local std::string g_last_hip_error;
+
+size_t elem_size(int dt) {
+    switch (dt) {
+        case DWT2_F32: return 4;
+        case DWT2_BF16: return 2;
+        case DWT2_F16: return 2;
+        case DWT2_I32: return 4;
+    }
+    return 0;
+}
+
+constexpr int32_t kMaxSide = 1 << 30;
+constexpr int64_t kWsAlign = 256;            // bytes; also the LL pitch granule
+
+int64_t ws_pitch(int32_t w) {                // elements, multiple of 64
+    return ((int64_t)w + 63) / 64 * 64;
+}
+
+struct Plan {
+    int levels;
+    int32_t h[32], w[32];                    // size transformed at each level
+};
+
+int max_levels(int32_t h, int32_t w) {
+    if (h < 2 || w < 2) return 0;
+    int n = 0;
+    while (h >= 2 && w >= 2) {
+        ++n;
+        h = (h + 1) / 2;
+        w = (w + 1) / 2;
+    }
+    return n;
+}
+
+void plan_levels(int32_t h, int32_t w, int levels, Plan* p) {
+    p->levels = levels;
+    for (int l = 0; l < levels; ++l) {
+        p->h[l] = h;
+        p->w[l] = w;
+        h = (h + 1) / 2;
+        w = (w + 1) / 2;
+    }
+}
+
+// Two ping-pong buffers for intermediate LL bands: buffer A holds the LL of
+// levels 1, 3, 5, ... (largest: level 1), buffer B of levels 2, 4, ...
+void ws_layout(const Plan& p, size_t es, size_t* off_b, size_t* total) {
+    size_t a = 0, b = 0;
+    for (int l = 0; l + 1 < p.levels; ++l) {  // LL of level l+1 (0-based l) is kept
+        const int32_t he = (p.h[l] + 1) / 2, we = (p.w[l] + 1) / 2;
+        const size_t sz = (size_t)he * (size_t)ws_pitch(we) * es;
+        if (l % 2 == 0) a = a > sz ? a : sz; else b = b > sz ? b : sz;
+    }
+    a = (a + kWsAlign - 1) / kWsAlign * kWsAlign;
+    *off_b = a;
+    *total = a + b;
+}
+
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+    if (!na || !nb) return false;
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+size_t span_bytes(int32_t h, int32_t w, int64_t pitch, size_t es) {
+    return ((size_t)(h - 1) * (size_t)pitch + (size_t)w) * es;
+}
+
+int validate(const void* src, void* dst, int32_t h, int32_t w, int64_t sp, int64_t dp,
+             int dtype, int wavelet, int levels, int boundary, unsigned flags,
+             const void* ws, size_t ws_bytes, bool adjoint) {
+    if (!src || !dst) return DWT2_E_NULL;
+    if (wavelet != DWT2_CDF97 && wavelet != DWT2_CDF53_REV) return DWT2_E_WAVELET;
+    if (dtype != DWT2_F32 && dtype != DWT2_BF16 && dtype != DWT2_F16 && dtype != DWT2_I32)
+        return DWT2_E_DTYPE;
+    if ((wavelet == DWT2_CDF53_REV) != (dtype == DWT2_I32)) return DWT2_E_DTYPE;
+    if (boundary != DWT2_SYMMETRIC_WHOLE) return DWT2_E_BOUNDARY;
+    if (flags & ~DWT2_FLAG_SPLIT) return DWT2_E_FLAGS;
+    if ((flags & DWT2_FLAG_SPLIT) && (wavelet != DWT2_CDF97 || adjoint)) return DWT2_E_FLAGS;
+    if (adjoint && wavelet != DWT2_CDF97) return DWT2_E_WAVELET;
+    if (h < 2 || w < 2 || h > kMaxSide || w > kMaxSide) return DWT2_E_SHAPE;
+    if (sp < w || dp < w) return DWT2_E_PITCH;
+    if (levels < 1 || levels > max_levels(h, w)) return DWT2_E_LEVELS;
+    size_t need = 0;
+    dwt2_workspace_bytes(h, w, levels, (dwt2_dtype)dtype, &need);
+    if (need > 0 && (!ws || ws_bytes < need)) return DWT2_E_WORKSPACE;
+    const size_t es = elem_size(dtype);
+    const size_t ns = span_bytes(h, w, sp, es), nd = span_bytes(h, w, dp, es);
+    if (ranges_overlap(src, ns, dst, nd)) return DWT2_E_ALIAS;
+    if (need > 0 && (ranges_overlap(ws, need, src, ns) || ranges_overlap(ws, need, dst, nd)))
+        return DWT2_E_ALIAS;
+    return DWT2_OK;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+int report(hipError_t e) {
+    if (e == hipSuccess) return DWT2_OK;
+    g_last_hip_error = hipGetErrorString(e);
+    return DWT2_E_HIP;
+}
+
+dwt2::Dtype to_dtype(int d) { return (dwt2::Dtype)d; }
+dwt2::Wavelet to_wav(int w) { return w == DWT2_CDF97 ? dwt2::kCdf97 : dwt2::kCdf53; }
+
+void tiles(int32_t h, int32_t w, int32_t* tx, int32_t* ty) {
+    const int32_t nEr = (h + 1) / 2, nEc = (w + 1) / 2;
+    *tx = (nEc + dwt2::kCoreBX - 1) / dwt2::kCoreBX;
+    *ty = (nEr + dwt2::kCoreBY - 1) / dwt2::kCoreBY;
+}
+
+// Forward: level l reads the LL of level l-1 (src for l = 0) and writes its
+// details into dst at the level's region origin (dst itself: every level's
+// region starts at (0, 0)), its LL into the workspace or, for the last level,
+// into dst.
+int run_forward(const void* src, void* dst, int32_t h, int32_t w, int64_t sp, int64_t dp,
+                int dtype, int wavelet, int levels, unsigned flags, void* ws, hipStream_t s) {
+    Plan p;
+    plan_levels(h, w, levels, &p);
+    const size_t es = elem_size(dtype);
+    size_t off_b = 0, total = 0;
+    ws_layout(p, es, &off_b, &total);
+    char* bufs[2] = {(char*)ws, (char*)ws + off_b};
+    const void* in = src;
+    int64_t in_pitch = sp;
+    for (int l = 0; l < levels; ++l) {
+        dwt2::LevelParams lp{};
+        lp.h = p.h[l];
+        lp.w = p.w[l];
+        lp.in = in;
+        lp.in_pitch = in_pitch;
+        lp.out = dst;
+        lp.out_pitch = dp;
+        const bool last = l + 1 == levels;
+        lp.out_ll = last ? dst : (void*)bufs[l % 2];
+        lp.out_ll_pitch = last ? dp : ws_pitch((lp.w + 1) / 2);
+        tiles(lp.h, lp.w, &lp.tiles_x, &lp.tiles_y);
+        const int32_t nEc = (lp.w + 1) / 2;
+        lp.vec = aligned(lp.in, 4 * es) && lp.in_pitch % 4 == 0 &&
+                 aligned(lp.out, 2 * es) && lp.out_pitch % 2 == 0 && nEc % 2 == 0 &&
+                 aligned(lp.out_ll, 2 * es) && lp.out_ll_pitch % 2 == 0;
+        const int rc = report(dwt2::launch_level(dwt2::kForward, to_wav(wavelet), to_dtype(dtype),
+                                                 (flags & DWT2_FLAG_SPLIT) != 0, lp, s));
+        if (rc) return rc;
+        in = lp.out_ll;
+        in_pitch = lp.out_ll_pitch;
+    }
+    return DWT2_OK;
+}
+
+// Inverse / adjoint: coarsest level first.  Level l reads its LL (src for the
+// coarsest level, else the workspace written by level l+1) and its details
+// from src, and writes its image into the workspace or, for l = 0, into dst.
+int run_backward(dwt2::Direction dir, const void* src, void* dst, int32_t h, int32_t w,
+                 int64_t sp, int64_t dp, int dtype, int wavelet, int levels, unsigned flags,
+                 void* ws, hipStream_t s) {
+    Plan p;
+    plan_levels(h, w, levels, &p);
+    const size_t es = elem_size(dtype);
+    size_t off_b = 0, total = 0;
+    ws_layout(p, es, &off_b, &total);
+    char* bufs[2] = {(char*)ws, (char*)ws + off_b};
+    const void* ll = src;
+    int64_t ll_pitch = sp;
+    for (int l = levels - 1; l >= 0; --l) {
+        dwt2::LevelParams lp{};
+        lp.h = p.h[l];
+        lp.w = p.w[l];
+        lp.in = src;
+        lp.in_pitch = sp;
+        lp.in_ll = ll;
+        lp.in_ll_pitch = ll_pitch;
+        // the image of level l is the LL of level l-1 (kept in buffer (l-1) % 2)
+        lp.out = l == 0 ? dst : (void*)bufs[(l - 1) % 2];
+        lp.out_pitch = l == 0 ? dp : ws_pitch(lp.w);
+        tiles(lp.h, lp.w, &lp.tiles_x, &lp.tiles_y);
+        const int32_t nEc = (lp.w + 1) / 2;
+        lp.vec = aligned(lp.in, 2 * es) && lp.in_pitch % 2 == 0 && nEc % 2 == 0 &&
+                 aligned(lp.in_ll, 2 * es) && lp.in_ll_pitch % 2 == 0 &&
+                 aligned(lp.out, 4 * es) && lp.out_pitch % 4 == 0;
+        const int rc = report(dwt2::launch_level(dir, to_wav(wavelet), to_dtype(dtype),
+                                                 (flags & DWT2_FLAG_SPLIT) != 0, lp, s));
+        if (rc) return rc;
+        ll = lp.out;
+        ll_pitch = lp.out_pitch;
+    }
+    return DWT2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dwt2_max_levels(int32_t height, int32_t width) { return max_levels(height, width); }
+
+int dwt2_workspace_bytes(int32_t height, int32_t width, int levels, dwt2_dtype dtype,
+                         size_t* bytes) {
+    if (!bytes) return DWT2_E_NULL;
+    *bytes = 0;
+    const size_t es = elem_size(dtype);
+    if (!es) return DWT2_E_DTYPE;
+    if (height < 2 || width < 2 || height > kMaxSide || width > kMaxSide) return DWT2_E_SHAPE;
+    if (levels < 1 || levels > max_levels(height, width)) return DWT2_E_LEVELS;
+    Plan p;
+    plan_levels(height, width, levels, &p);
+    size_t off_b = 0, total = 0;
+    ws_layout(p, es, &off_b, &total);
+    *bytes = total;
+    return DWT2_OK;
+}
+
+int dwt2_fwd(const void* src, void* dst, int32_t height, int32_t width, int64_t src_pitch,
+             int64_t dst_pitch, dwt2_dtype dtype, dwt2_wavelet wavelet, int levels,
+             dwt2_boundary boundary, unsigned flags, void* workspace, size_t workspace_bytes,
+             void* stream) {
+    const int rc = validate(src, dst, height, width, src_pitch, dst_pitch, dtype, wavelet, levels,
+                            boundary, flags, workspace, workspace_bytes, false);
+    if (rc) return rc;
+    return run_forward(src, dst, height, width, src_pitch, dst_pitch, dtype, wavelet, levels,
+                       flags, workspace, (hipStream_t)stream);
+}
+
+int dwt2_inv(const void* src, void* dst, int32_t height, int32_t width, int64_t src_pitch,
+             int64_t dst_pitch, dwt2_dtype dtype, dwt2_wavelet wavelet, int levels,
+             dwt2_boundary boundary, unsigned flags, void* workspace, size_t workspace_bytes,
+             void* stream) {
+    const int rc = validate(src, dst, height, width, src_pitch, dst_pitch, dtype, wavelet, levels,
+                            boundary, flags, workspace, workspace_bytes, false);
+    if (rc) return rc;
+    return run_backward(dwt2::kInverse, src, dst, height, width, src_pitch, dst_pitch, dtype,
+                        wavelet, levels, flags, workspace, (hipStream_t)stream);
+}
+
+int dwt2_adj(const void* src, void* dst, int32_t height, int32_t width, int64_t src_pitch,
+             int64_t dst_pitch, dwt2_dtype dtype, dwt2_wavelet wavelet, int levels,
+             dwt2_boundary boundary, unsigned flags, void* workspace, size_t workspace_bytes,
+             void* stream) {
+    const int rc = validate(src, dst, height, width, src_pitch, dst_pitch, dtype, wavelet, levels,
+                            boundary, flags, workspace, workspace_bytes, true);
+    if (rc) return rc;
+    return run_backward(dwt2::kAdjoint, src, dst, height, width, src_pitch, dst_pitch, dtype,
+                        wavelet, levels, flags, workspace, (hipStream_t)stream);
+}
+
+const char* dwt2_status_string(int status) {
+    switch (status) {
+        case DWT2_OK: return "ok";
+        case DWT2_E_NULL: return "null pointer";
+        case DWT2_E_SHAPE: return "height and width must be in [2, 2^30]";
+        case DWT2_E_LEVELS: return "level count out of range for this shape";
+        case DWT2_E_DTYPE: return "dtype not valid for this wavelet";
+        case DWT2_E_WAVELET: return "unknown or unsupported wavelet";
+        case DWT2_E_BOUNDARY: return "unknown boundary extension";
+        case DWT2_E_PITCH: return "pitch smaller than width";
+        case DWT2_E_WORKSPACE: return "workspace missing or too small";
+        case DWT2_E_ALIAS: return "src, dst and workspace must not overlap";
+        case DWT2_E_HIP: return "HIP runtime error";
+        case DWT2_E_FLAGS: return "flags not valid for this call";
+        case DWT2_E_COUNT: return "image count must be positive";
+    }
+    return "unknown status";
+}
+
+const char* dwt2_last_hip_error(void) { return g_last_hip_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/dwt2.h declares, and rejects every invalid call before touching HIP
+(no compute call runs here: each call below fails its argument checks)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1704_08657_amd as d
+from oracle import lifting
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dwt2.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(d.LIB_PATH), reason="libdwt2.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(dwt2_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert {"dwt2_fwd", "dwt2_inv", "dwt2_adj", "dwt2_max_levels", "dwt2_workspace_bytes"} <= set(names)
+    L = d.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    # the binding wraps every declared function with a signature
+    assert set(names) <= set(d.SIGNATURES)
+
+
+@pytest.mark.parametrize("h,w", [(1, 5), (2, 2), (3, 2), (5, 7), (64, 66), (8192, 8192), (2, 1 << 20), (1000, 3)])
+def test_max_levels_matches_oracle(h, w):
+    expect = lifting.max_levels(h, w) if h >= 2 and w >= 2 else 0
+    assert d.dwt2_max_levels(h, w) == expect
+
+
+def test_workspace_bytes():
+    st, n = d.dwt2_workspace_bytes(512, 512, 1, d.DWT2_F32)
+    assert st == 0 and n == 0
+    st, n = d.dwt2_workspace_bytes(8192, 8192, 5, d.DWT2_F32)
+    # LL of level 1 (4096 x 4096) and level 2 (2048 x 2048), pitch multiple of 64
+    assert st == 0 and n == 4096 * 4096 * 4 + 2048 * 2048 * 4
+    st, n = d.dwt2_workspace_bytes(8192, 8192, 5, d.DWT2_BF16)
+    assert st == 0 and n == (4096 * 4096 + 2048 * 2048) * 2
+    st, _ = d.dwt2_workspace_bytes(8192, 8192, 14, d.DWT2_F32)
+    assert st == -3
+    st, _ = d.dwt2_workspace_bytes(1, 8, 1, d.DWT2_F32)
+    assert st == -2
+    st, _ = d.dwt2_workspace_bytes(8, 8, 1, 9)
+    assert st == -4
+
+
+FAKE_SRC = 0x10000000
+FAKE_DST = 0x20000000
+FAKE_WS = 0x30000000
+
+
+def call(fn=d.dwt2_fwd, src=FAKE_SRC, dst=FAKE_DST, h=64, w=64, sp=64, dp=64, dtype=d.DWT2_F32,
+         wav=d.DWT2_CDF97, levels=1, boundary=0, flags=0, ws=0, ws_n=0):
+    return fn(ctypes.c_void_p(src), ctypes.c_void_p(dst), h, w, sp, dp, dtype, wav, levels, boundary,
+              flags, ctypes.c_void_p(ws), ws_n, None)
+
+
+@pytest.mark.parametrize("fn", [d.dwt2_fwd, d.dwt2_inv, d.dwt2_adj])
+def test_argument_errors(fn):
+    assert call(fn, src=0) == -1
+    assert call(fn, dst=0) == -1
+    assert call(fn, h=1) == -2
+    assert call(fn, w=0) == -2
+    assert call(fn, sp=63) == -7
+    assert call(fn, dp=10) == -7
+    assert call(fn, levels=0) == -3
+    assert call(fn, levels=7) == -3          # 64 x 64 allows 6
+    assert call(fn, boundary=1) == -6
+    assert call(fn, dtype=7) == -4
+    assert call(fn, flags=4) == -11
+    # workspace required for 2 levels
+    assert call(fn, levels=2) == -8
+    assert call(fn, levels=2, ws=FAKE_WS, ws_n=10) == -8
+    # overlapping src / dst
+    assert call(fn, dst=FAKE_SRC + 64 * 4) == -9
+    # workspace overlapping dst
+    st, n = d.dwt2_workspace_bytes(64, 64, 2, d.DWT2_F32)
+    assert call(fn, levels=2, ws=FAKE_DST + 16, ws_n=n) == -9
+
+
+def test_wavelet_dtype_pairs():
+    assert call(dtype=d.DWT2_I32, wav=d.DWT2_CDF97) == -4
+    assert call(dtype=d.DWT2_F32, wav=d.DWT2_CDF53_REV) == -4
+    assert call(dtype=d.DWT2_BF16, wav=d.DWT2_CDF53_REV) == -4
+    assert call(wav=5) == -5
+    # the adjoint is defined for the linear CDF 9/7 only
+    assert call(d.dwt2_adj, dtype=d.DWT2_I32, wav=d.DWT2_CDF53_REV) == -5
+    # the split is a CDF 9/7 forward / inverse option
+    assert call(dtype=d.DWT2_I32, wav=d.DWT2_CDF53_REV, flags=d.DWT2_FLAG_SPLIT) == -11
+    assert call(d.dwt2_adj, flags=d.DWT2_FLAG_SPLIT) == -11
+
+
+def test_status_strings():
+    for s in range(0, -13, -1):
+        assert d.status_string(s) != "unknown status"
+    assert d.status_string(-99) == "unknown status"
+
+
+def test_tensor_api_refuses_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(RuntimeError, match="GPU only"):
+        d.fwd(torch.zeros(8, 8))

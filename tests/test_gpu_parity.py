@@ -1,0 +1,212 @@
+"""GPU parity: the HIP kernels (through the C ABI) against the CPU oracle.
+
+Bars: reversible CDF 5/3 bit-exact; CDF 9/7 with FP32 storage within
+max|gpu - oracle| / max|oracle| <= 1e-5 per image (all levels); BF16 / FP16
+storage within the rounding bound derived in test_storage_bound below.
+Inputs are seeded synthetic images (workloads).  Large images are checked on
+crops (corners, edge midpoints, centre) that the oracle evaluates exactly.
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import adjoint, lifting, window
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1704_08657_amd as d  # noqa: E402
+
+TOL97 = 1e-5
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(got, ref):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def gpu(x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x)).to(dev())
+    return t if dtype is None else t.to(dtype)
+
+
+def host(t):
+    return t.detach().to("cpu").to(torch.float64 if t.is_floating_point() else torch.int64).numpy()
+
+
+SMALL = [(2, 2), (2, 3), (3, 2), (3, 3), (5, 7), (8, 8), (9, 4), (17, 33), (64, 66),
+         (130, 250), (255, 257), (300, 1000), (512, 512)]
+
+
+def levels_for(h, w):
+    m = lifting.max_levels(h, w)
+    return sorted({1, min(m, 5), m})
+
+
+@pytest.mark.parametrize("shape", SMALL)
+@pytest.mark.parametrize("split", [False, True])
+def test_fwd_inv_cdf97_f32(shape, split):
+    h, w = shape
+    x = workloads.uniform(h, w, seed=h * 1000 + w)
+    for lv in levels_for(h, w):
+        say("cdf97 f32", shape, "levels", lv, "split", split)
+        ref = lifting.fwd(x, "cdf97", lv)
+        y = d.fwd(gpu(x), "cdf97", lv, split=split)
+        torch.cuda.synchronize()
+        assert rel_err(host(y), ref) <= TOL97
+        # inverse of the oracle's coefficients (as FP32)
+        c = ref.astype(np.float32)
+        xr = d.inv(gpu(c), "cdf97", lv, split=split)
+        torch.cuda.synchronize()
+        assert rel_err(host(xr), lifting.inv(c, "cdf97", lv)) <= TOL97
+
+
+@pytest.mark.parametrize("shape", SMALL + [(31, 2), (2, 77), (1023, 1025)])
+def test_cdf53_bit_exact(shape):
+    h, w = shape
+    for lo, hi in [(0, 256), (-3000, 3000)]:
+        x = workloads.integers(h, w, lo, hi, seed=h + 7 * w)
+        for lv in levels_for(h, w):
+            say("cdf53", shape, "levels", lv, "range", lo, hi)
+            ref = lifting.fwd(x, "cdf53", lv)
+            y = host(d.fwd(gpu(x), "cdf53", lv))
+            assert np.array_equal(y, ref)
+            xr = host(d.inv(gpu(ref.astype(np.int32)), "cdf53", lv))
+            assert np.array_equal(xr, x)
+
+
+@pytest.mark.parametrize("shape", SMALL)
+def test_adjoint_cdf97_f32(shape):
+    h, w = shape
+    g = workloads.uniform(h, w, seed=3 * h + w) - np.float32(0.5)
+    for lv in levels_for(h, w):
+        say("adj", shape, "levels", lv)
+        ref = adjoint.adj(g, "cdf97", lv)
+        got = host(d.adj(gpu(g), lv))
+        assert rel_err(got, ref) <= TOL97
+
+
+def test_adjoint_dot_product_on_gpu():
+    h, w, lv = 96, 130, 3
+    x = workloads.uniform(h, w, seed=1) - np.float32(0.5)
+    y = workloads.uniform(h, w, seed=2) - np.float32(0.5)
+    wx = host(d.fwd(gpu(x), "cdf97", lv))
+    wty = host(d.adj(gpu(y), lv))
+    lhs = float(np.vdot(wx, y))
+    rhs = float(np.vdot(x, wty))
+    assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), 1.0)
+
+
+# BF16 keeps 8 significant bits (unit roundoff 2^-9), FP16 11 (2^-12).  Every
+# stored coefficient carries one rounding relative to its own magnitude, and
+# the LL of each level is rounded before the next level reads it; the next
+# level's filters (DC gain 2 per level in 2-D, l1 norm of the 2-D low-pass
+# ~ 2.6) amplify that input error.  A bound of 8 unit roundoffs of the largest
+# coefficient covers one level plus the propagated LL rounding of up to five
+# levels with margin; it is a factor ~30 below a dropped term's error.
+UNIT = {torch.bfloat16: 2.0 ** -9, torch.float16: 2.0 ** -12}
+
+
+@pytest.mark.parametrize("tdt", [torch.bfloat16, torch.float16])
+@pytest.mark.parametrize("shape,lv", [((512, 512), 1), ((512, 512), 5), ((300, 1000), 3), ((17, 33), 2)])
+def test_storage_bound(tdt, shape, lv):
+    h, w = shape
+    x32 = workloads.uniform(h, w, seed=11)
+    xs = torch.from_numpy(x32).to(tdt)                  # storage-rounded input
+    xs64 = xs.to(torch.float64).numpy()
+    say("storage", tdt, shape, lv)
+    ref = lifting.fwd(xs64, "cdf97", lv)
+    y = host(d.fwd(xs.to(dev()), "cdf97", lv))
+    assert rel_err(y, ref) <= 8 * UNIT[tdt]
+    # inverse of the oracle's (storage-rounded) coefficients
+    cs = torch.from_numpy(ref).to(tdt)
+    xr = host(d.inv(cs.to(dev()), "cdf97", lv))
+    assert rel_err(xr, lifting.inv(cs.to(torch.float64).numpy(), "cdf97", lv)) <= 8 * UNIT[tdt]
+
+
+def test_pitched_buffers():
+    """src / dst rows padded (pitch > width) through the raw C ABI."""
+    h, w, lv = 200, 301, 3
+    x = workloads.uniform(h, w, seed=5)
+    src = torch.zeros(h, 320, device=dev())
+    src[:, :w] = gpu(x)
+    dst = torch.full((h, 333), float("nan"), device=dev())
+    ws = d.workspace(h, w, lv, d.DWT2_F32, dev())
+    st = d.dwt2_fwd(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), h, w, 320, 333,
+                    d.DWT2_F32, d.DWT2_CDF97, lv, 0, 0, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                    ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0
+    torch.cuda.synchronize()
+    got = host(dst)
+    assert rel_err(got[:, :w], lifting.fwd(x, "cdf97", lv)) <= TOL97
+    assert np.isnan(got[:, w:]).all()                   # padding untouched
+
+
+def test_nan_poisoned_outputs_are_all_written():
+    h, w = 257, 391
+    x = workloads.uniform(h, w, seed=6)
+    out = torch.full((h, w), float("nan"), device=dev())
+    d.fwd(gpu(x), "cdf97", 4, out=out)
+    assert not torch.isnan(out).any().item()
+    back = torch.full((h, w), float("nan"), device=dev())
+    d.inv(out, "cdf97", 4, out=back)
+    assert not torch.isnan(back).any().item()
+
+
+# ---- full-size images: sampled parity on crops -----------------------------
+
+def crop_check(x, y_gpu, wavelet, lv, tol):
+    H, W = x.shape
+    m = window.default_margin(lv)
+    worst = 0.0
+    for r0, r1, c0, c1 in window.probe_crops(H, W, lv, size=256):
+        sub = lifting.fwd(x[r0:r1, c0:c1], wavelet, lv)
+        cut = window.crop_pyramid(y_gpu, lv, r0, r1, c0, c1)
+        mask = window.crop_valid_mask(H, W, lv, r0, r1, c0, c1, m)
+        if wavelet == "cdf53":
+            assert np.array_equal(cut[mask], sub[mask]), (r0, c0)
+        else:
+            worst = max(worst, float(np.abs(cut[mask] - sub[mask]).max()))
+    return worst
+
+
+@pytest.mark.parametrize("n", [4096, 8192])
+@pytest.mark.parametrize("lv", [1, 5])
+def test_full_size_cdf97_crops(n, lv):
+    x = workloads.uniform(n, n, seed=0)
+    say("full-size cdf97", n, lv)
+    y = d.fwd(gpu(x), "cdf97", lv)
+    yh = host(y)
+    # relative to the largest coefficient of the whole pyramid (LL grows 2x per level)
+    scale = float(np.abs(yh).max())
+    worst = crop_check(x, yh, "cdf97", lv, TOL97)
+    assert worst / scale <= TOL97
+    # the inverse brings the image back (property at any size)
+    xr = host(d.inv(y, "cdf97", lv))
+    assert np.abs(xr - x).max() <= 1e-4
+
+
+@pytest.mark.parametrize("lv", [1, 5])
+def test_full_size_cdf53_crops(lv):
+    n = 8192
+    x = workloads.pixels_u8(n, n, seed=0)
+    say("full-size cdf53", n, lv)
+    y = d.fwd(gpu(x), "cdf53", lv)
+    crop_check(x, host(y), "cdf53", lv, 0)
+    xr = d.inv(y, "cdf53", lv)
+    assert torch.equal(xr.cpu(), torch.from_numpy(x))
