@@ -89,7 +89,15 @@ typedef enum {
 /* Flags (bitwise or). */
 #define DWT2_FLAG_SPLIT 1u   /* P = P0 + P1, U = U0 + U1 operation-count reduction
                                 (Section "Optimization Approach"); CDF 9/7 only.
-                                Same values up to FP32 rounding.               */
+                                Same values up to FP32 rounding; applied in tiles
+                                away from the image border.                    */
+/* Tile shape: bits 8..15 hold 1 + the index of a shape listed by
+ * dwt2_tile_shape(); 0 selects the library default.  Every shape computes the
+ * same values (bit-identical for the same flags otherwise). */
+#define DWT2_FLAG_TILE_SHIFT 8
+#define DWT2_FLAG_TILE_MASK 0xff00u
+#define DWT2_FLAG_TILE(i) (((unsigned)(i) + 1u) << DWT2_FLAG_TILE_SHIFT)
+#define DWT2_NUM_TILE_SHAPES 6
 
 /* One image of a batched call.  Pitches in elements. */
 typedef struct {
@@ -139,6 +147,12 @@ int dwt2_adj(const void* src, void* dst, int32_t height, int32_t width,
              dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,
              unsigned flags, void* workspace, size_t workspace_bytes,
              void* stream);
+
+/* Describe tile shape `index` (0 .. DWT2_NUM_TILE_SHAPES-1): wave64s per
+ * work-group, block rows held per lane, and the core (output) size of one tile
+ * in 2x2-pixel blocks.  Any output pointer may be NULL.  Returns DWT2_OK or
+ * DWT2_E_FLAGS for an unknown index. */
+int dwt2_tile_shape(int index, int* waves, int* rows_per_lane, int* core_cols, int* core_rows);
 
 /* Text of a dwt2_status. */
 const char* dwt2_status_string(int status);

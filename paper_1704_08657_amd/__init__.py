@@ -27,6 +27,12 @@ DWT2_CDF97, DWT2_CDF53_REV = 0, 1
 DWT2_F32, DWT2_BF16, DWT2_F16, DWT2_I32 = 0, 1, 2, 3
 DWT2_SYMMETRIC_WHOLE = 0
 DWT2_FLAG_SPLIT = 1
+DWT2_FLAG_TILE_SHIFT = 8
+DWT2_NUM_TILE_SHAPES = 6
+
+
+def DWT2_FLAG_TILE(i: int) -> int:
+    return (i + 1) << DWT2_FLAG_TILE_SHIFT
 
 WAVELETS = {"cdf97": DWT2_CDF97, "cdf53": DWT2_CDF53_REV}
 
@@ -41,6 +47,7 @@ SIGNATURES = {
     "dwt2_fwd": (_c_int, _TRANSFORM_ARGS),
     "dwt2_inv": (_c_int, _TRANSFORM_ARGS),
     "dwt2_adj": (_c_int, _TRANSFORM_ARGS),
+    "dwt2_tile_shape": (_c_int, [_c_int] + [ctypes.POINTER(_c_int)] * 4),
     "dwt2_status_string": (ctypes.c_char_p, [_c_int]),
     "dwt2_last_hip_error": (ctypes.c_char_p, []),
 }
@@ -97,6 +104,13 @@ def dwt2_adj(*args) -> int:
     return lib().dwt2_adj(*args)
 
 
+def dwt2_tile_shape(index: int):
+    """(status, waves, rows_per_lane, core_cols, core_rows) of a tile shape."""
+    v = [ctypes.c_int(0) for _ in range(4)]
+    st = lib().dwt2_tile_shape(index, *[ctypes.byref(x) for x in v])
+    return (st, *[x.value for x in v])
+
+
 def status_string(status: int) -> str:
     return lib().dwt2_status_string(status).decode()
 
@@ -142,7 +156,7 @@ def workspace(h: int, w: int, levels: int, dtype, device):
     return torch.empty(n, dtype=torch.uint8, device=device)
 
 
-def _transform(fn, name, x, wavelet, levels, split, out):
+def _transform(fn, name, x, wavelet, levels, split, out, tile=None):
     torch = _torch()
     _check(x)
     x2 = x.reshape(-1, *x.shape[-2:]) if x.is_contiguous() else x.contiguous().reshape(-1, *x.shape[-2:])
@@ -160,6 +174,8 @@ def _transform(fn, name, x, wavelet, levels, split, out):
     ws_n = ws.numel() if ws is not None else 0
     stream = _stream_ptr(x2)
     flags = DWT2_FLAG_SPLIT if split else 0
+    if tile is not None:
+        flags |= DWT2_FLAG_TILE(tile)
     for i in range(x2.shape[0]):
         st = fn(ctypes.c_void_p(x2[i].data_ptr()), ctypes.c_void_p(out[i].data_ptr()), H, W,
                 x2.stride(-2), out.stride(-2), dt, WAVELETS[wavelet], levels,
@@ -169,19 +185,20 @@ def _transform(fn, name, x, wavelet, levels, split, out):
     return out.reshape(x.shape)
 
 
-def fwd(x, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None):
-    """Forward transform of every [H, W] plane of x into a Mallat pyramid."""
-    return _transform(dwt2_fwd, "dwt2_fwd", x, wavelet, levels, split, out)
+def fwd(x, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, tile=None):
+    """Forward transform of every [H, W] plane of x into a Mallat pyramid.
+    `tile` selects a tile shape index (None: library default)."""
+    return _transform(dwt2_fwd, "dwt2_fwd", x, wavelet, levels, split, out, tile)
 
 
-def inv(c, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None):
+def inv(c, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, tile=None):
     """Inverse transform of every [H, W] Mallat pyramid of c."""
-    return _transform(dwt2_inv, "dwt2_inv", c, wavelet, levels, split, out)
+    return _transform(dwt2_inv, "dwt2_inv", c, wavelet, levels, split, out, tile)
 
 
-def adj(g, levels: int = 1, out=None):
+def adj(g, levels: int = 1, out=None, tile=None):
     """Adjoint W^T g of the CDF 9/7 forward transform (cotangent in Mallat layout)."""
-    return _transform(dwt2_adj, "dwt2_adj", g, "cdf97", levels, False, out)
+    return _transform(dwt2_adj, "dwt2_adj", g, "cdf97", levels, False, out, tile)
 
 
 def _make_function():

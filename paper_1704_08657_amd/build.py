@@ -20,6 +20,10 @@ SOURCES = ["dwt2_kernels.hip", "dwt2_api.cpp"]
 # Packed FP32 instructions are disabled for every HIP translation unit.
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # every fused multiply-add is written out (fmaf): no implicit
+             # contraction, so each coefficient's rounding is the same in
+             # every code path and tile shape
+             "-ffp-contract=off",
              "-Wall", "-Wno-unused-function",
              f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 

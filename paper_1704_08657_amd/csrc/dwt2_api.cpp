@@ -11,6 +11,8 @@
 #include "../../include/dwt2.h"
 #include "dwt2_internal.h"
 
+static_assert(DWT2_NUM_TILE_SHAPES == dwt2::kNumTileShapes, "tile shape count in dwt2.h");
+
 namespace {
 
 thread_local std::string g_last_hip_error;
@@ -91,7 +93,9 @@ int validate(const void* src, void* dst, int32_t h, int32_t w, int64_t sp, int64
         return DWT2_E_DTYPE;
     if ((wavelet == DWT2_CDF53_REV) != (dtype == DWT2_I32)) return DWT2_E_DTYPE;
     if (boundary != DWT2_SYMMETRIC_WHOLE) return DWT2_E_BOUNDARY;
-    if (flags & ~DWT2_FLAG_SPLIT) return DWT2_E_FLAGS;
+    if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_TILE_MASK)) return DWT2_E_FLAGS;
+    if (((flags & DWT2_FLAG_TILE_MASK) >> DWT2_FLAG_TILE_SHIFT) > (unsigned)dwt2::kNumTileShapes)
+        return DWT2_E_FLAGS;
     if ((flags & DWT2_FLAG_SPLIT) && (wavelet != DWT2_CDF97 || adjoint)) return DWT2_E_FLAGS;
     if (adjoint && wavelet != DWT2_CDF97) return DWT2_E_WAVELET;
     if (h < 2 || w < 2 || h > kMaxSide || w > kMaxSide) return DWT2_E_SHAPE;
@@ -119,10 +123,17 @@ int report(hipError_t e) {
 dwt2::Dtype to_dtype(int d) { return (dwt2::Dtype)d; }
 dwt2::Wavelet to_wav(int w) { return w == DWT2_CDF97 ? dwt2::kCdf97 : dwt2::kCdf53; }
 
-void tiles(int32_t h, int32_t w, int32_t* tx, int32_t* ty) {
+void tiles(int shape, int32_t h, int32_t w, int32_t* tx, int32_t* ty) {
     const int32_t nEr = (h + 1) / 2, nEc = (w + 1) / 2;
+    const int cy = dwt2::core_rows(dwt2::kTileShapes[shape]);
     *tx = (nEc + dwt2::kCoreBX - 1) / dwt2::kCoreBX;
-    *ty = (nEr + dwt2::kCoreBY - 1) / dwt2::kCoreBY;
+    *ty = (nEr + cy - 1) / cy;
+}
+
+// Tile shape selected by the flags (0 in the tile field = library default).
+int shape_of(unsigned flags) {
+    const unsigned t = (flags >> DWT2_FLAG_TILE_SHIFT) & 0xffu;
+    return t == 0 ? dwt2::kDefaultTileShape : (int)t - 1;
 }
 
 // Forward: level l reads the LL of level l-1 (src for l = 0) and writes its
@@ -150,13 +161,13 @@ int run_forward(const void* src, void* dst, int32_t h, int32_t w, int64_t sp, in
         const bool last = l + 1 == levels;
         lp.out_ll = last ? dst : (void*)bufs[l % 2];
         lp.out_ll_pitch = last ? dp : ws_pitch((lp.w + 1) / 2);
-        tiles(lp.h, lp.w, &lp.tiles_x, &lp.tiles_y);
+        tiles(shape_of(flags), lp.h, lp.w, &lp.tiles_x, &lp.tiles_y);
         const int32_t nEc = (lp.w + 1) / 2;
         lp.vec = aligned(lp.in, 4 * es) && lp.in_pitch % 4 == 0 &&
                  aligned(lp.out, 2 * es) && lp.out_pitch % 2 == 0 && nEc % 2 == 0 &&
                  aligned(lp.out_ll, 2 * es) && lp.out_ll_pitch % 2 == 0;
         const int rc = report(dwt2::launch_level(dwt2::kForward, to_wav(wavelet), to_dtype(dtype),
-                                                 (flags & DWT2_FLAG_SPLIT) != 0, lp, s));
+                                                 (flags & DWT2_FLAG_SPLIT) != 0, shape_of(flags), lp, s));
         if (rc) return rc;
         in = lp.out_ll;
         in_pitch = lp.out_ll_pitch;
@@ -189,13 +200,13 @@ int run_backward(dwt2::Direction dir, const void* src, void* dst, int32_t h, int
         // the image of level l is the LL of level l-1 (kept in buffer (l-1) % 2)
         lp.out = l == 0 ? dst : (void*)bufs[(l - 1) % 2];
         lp.out_pitch = l == 0 ? dp : ws_pitch(lp.w);
-        tiles(lp.h, lp.w, &lp.tiles_x, &lp.tiles_y);
+        tiles(shape_of(flags), lp.h, lp.w, &lp.tiles_x, &lp.tiles_y);
         const int32_t nEc = (lp.w + 1) / 2;
         lp.vec = aligned(lp.in, 2 * es) && lp.in_pitch % 2 == 0 && nEc % 2 == 0 &&
                  aligned(lp.in_ll, 2 * es) && lp.in_ll_pitch % 2 == 0 &&
                  aligned(lp.out, 4 * es) && lp.out_pitch % 4 == 0;
         const int rc = report(dwt2::launch_level(dir, to_wav(wavelet), to_dtype(dtype),
-                                                 (flags & DWT2_FLAG_SPLIT) != 0, lp, s));
+                                                 (flags & DWT2_FLAG_SPLIT) != 0, shape_of(flags), lp, s));
         if (rc) return rc;
         ll = lp.out;
         ll_pitch = lp.out_pitch;
@@ -256,6 +267,16 @@ int dwt2_adj(const void* src, void* dst, int32_t height, int32_t width, int64_t 
     if (rc) return rc;
     return run_backward(dwt2::kAdjoint, src, dst, height, width, src_pitch, dst_pitch, dtype,
                         wavelet, levels, flags, workspace, (hipStream_t)stream);
+}
+
+int dwt2_tile_shape(int index, int* waves, int* rows_per_lane, int* core_cols, int* core_rows) {
+    if (index < 0 || index >= dwt2::kNumTileShapes) return DWT2_E_FLAGS;
+    const dwt2::TileShape t = dwt2::kTileShapes[index];
+    if (waves) *waves = t.waves;
+    if (rows_per_lane) *rows_per_lane = t.rows;
+    if (core_cols) *core_cols = dwt2::kCoreBX;
+    if (core_rows) *core_rows = dwt2::core_rows(t);
+    return DWT2_OK;
 }
 
 const char* dwt2_status_string(int status) {

@@ -12,18 +12,23 @@ enum Wavelet : int { kCdf97 = 0, kCdf53 = 1 };
 enum Dtype : int { kF32 = 0, kBF16 = 1, kF16 = 2, kI32 = 3 };
 
 // Tile geometry shared by host planning and the kernels.  A work-group of
-// kWaves wave64s owns a tile of kTileBX x (kWaves * kRowsPerLane) blocks of
-// 2x2 pixels, of which a halo of kHalo blocks on every side is recomputed and
-// discarded.  Each lane holds two horizontally adjacent blocks for
-// kRowsPerLane consecutive block rows.
+// `waves` wave64s owns a tile of kTileBX x (waves * rows) blocks of 2x2
+// pixels, of which a halo of kHalo blocks on every side is recomputed and
+// discarded.  Each lane holds two horizontally adjacent blocks for `rows`
+// consecutive block rows.
 constexpr int kLanes = 64;
-constexpr int kWaves = 8;
-constexpr int kRowsPerLane = 8;
 constexpr int kHalo = 2;
 constexpr int kTileBX = 2 * kLanes;                       // 128 blocks
-constexpr int kTileBY = kWaves * kRowsPerLane;            // 64 blocks
 constexpr int kCoreBX = kTileBX - 2 * kHalo;              // 124 blocks
-constexpr int kCoreBY = kTileBY - 2 * kHalo;              // 60 blocks
+
+struct TileShape {
+    int waves;   // wave64s per work-group, stacked vertically
+    int rows;    // block rows per lane
+};
+constexpr TileShape kTileShapes[] = {{8, 8}, {4, 8}, {8, 4}, {16, 4}, {16, 2}, {4, 4}};
+constexpr int kNumTileShapes = 6;
+constexpr int kDefaultTileShape = 0;
+constexpr int core_rows(TileShape s) { return s.waves * s.rows - 2 * kHalo; }
 
 // One level of a transform.  Forward: `in` is the h x w image of this level,
 // `out` the origin of this level's region of the Mallat pyramid (details are
@@ -44,7 +49,8 @@ struct LevelParams {
 };
 
 // Enqueue one level.  Returns hipSuccess or the launch error.
-hipError_t launch_level(Direction dir, Wavelet wav, Dtype dt, bool split,
+// `shape` indexes kTileShapes; tiles_x / tiles_y of `p` must follow it.
+hipError_t launch_level(Direction dir, Wavelet wav, Dtype dt, bool split, int shape,
                         const LevelParams& p, hipStream_t stream);
 
 }  // namespace dwt2

@@ -10,11 +10,11 @@
 // `split` variant.
 //
 // Mapping to gfx950 (not the paper's OpenCL or shader design):
-//   * one work-group = kWaves wave64s = one tile of 128 x 64 blocks
-//     (256 x 128 pixels) with a 2-block halo recomputed on every side;
-//   * each lane owns two horizontally adjacent blocks ("L" and "R") for
-//     kRowsPerLane consecutive block rows, all in VGPRs: 8 rows x 2 blocks x
-//     4 components;
+//   * one work-group = NW wave64s = one tile of 128 x (NW * K) blocks
+//     (e.g. 256 x 128 pixels for NW = K = 8) with a 2-block halo recomputed
+//     on every side;
+//   * each lane owns two horizontally adjacent blocks ("L" and "R") for K
+//     consecutive block rows, all in VGPRs: K rows x 2 blocks x 4 components;
 //   * a step reads neighbours at +1 (predict-shaped: right / down) or at -1
 //     (update-shaped: left / up).  Horizontal neighbours come from the
 //     adjacent lane through DPP wave shifts, vertical ones from the lane's own
@@ -52,8 +52,6 @@ constexpr double kZeta = 1.1496043988602418;
 constexpr float kZeta2 = (float)(kZeta * kZeta);
 constexpr float kZetaM2 = (float)(1.0 / (kZeta * kZeta));
 
-constexpr int K = kRowsPerLane;
-constexpr int NW = kWaves;
 
 // ---------------------------------------------------------------------------
 // storage types
@@ -140,11 +138,12 @@ __device__ __forceinline__ void plus_block(V& x0, V& x1, V& x2, V& x3,
             ber = (float)((gr + 1 < g.nEr) + (gr + 1 == g.nOr && g.nEr > g.nOr));
         }
         const float cc = c * c;
-        const V h0 = alc * x0 + bec * x0R;
-        const V h0d = alc * x0D + bec * x0DR;
-        x3 += cc * (alr * h0 + ber * h0d) + c * (alr * x1 + ber * x1D) + c * (alc * x2 + bec * x2R);
-        x1 += c * h0;
-        x2 += c * (alr * x0 + ber * x0D);
+        const V h0 = fmaf(bec, x0R, alc * x0);
+        const V h0d = fmaf(bec, x0DR, alc * x0D);
+        x3 = fmaf(cc, fmaf(ber, h0d, alr * h0),
+                  fmaf(c, fmaf(ber, x1D, alr * x1), fmaf(c, fmaf(bec, x2R, alc * x2), x3)));
+        x1 = fmaf(c, h0, x1);
+        x2 = fmaf(c, fmaf(ber, x0D, alr * x0), x2);
     } else {
         if constexpr (EDGE) {
             const bool cR = gc + 1 < g.nEc;
@@ -157,13 +156,15 @@ __device__ __forceinline__ void plus_block(V& x0, V& x1, V& x2, V& x3,
         }
         if constexpr (KIND == kFloat) {
             const float cc = c * c;
-            x3 += cc * ((x0 + x0R) + (x0D + x0DR)) + c * (x1 + x1D) + c * (x2 + x2R);
-            x1 += c * (x0 + x0R);
-            x2 += c * (x0 + x0D);
+            const V t0 = x0 + x0R;
+            const V t1 = x0D + x0DR;
+            x3 = fmaf(cc, t0 + t1, fmaf(c, x1 + x1D, fmaf(c, x2 + x2R, x3)));
+            x1 = fmaf(c, t0, x1);
+            x2 = fmaf(c, x0 + x0D, x2);
         } else if constexpr (KIND == kSplit) {
-            x3 += (c * c) * x0DR + c * x1D + c * x2R;
-            x1 += c * x0R;
-            x2 += c * x0D;
+            x3 = fmaf(c * c, x0DR, fmaf(c, x1D, fmaf(c, x2R, x3)));
+            x1 = fmaf(c, x0R, x1);
+            x2 = fmaf(c, x0D, x2);
         } else if constexpr (KIND == kIntFwd) {
             // T^H then T^V; x1 one row down after T^H is recomputed.
             const V x1h = x1 - ((x0 + x0R) >> 1);
@@ -201,11 +202,12 @@ __device__ __forceinline__ void minus_block(V& x0, V& x1, V& x2, V& x3,
             br = (gr >= 1) ? 1.f : 0.f;
         }
         const float cc = c * c;
-        const V h3 = ac * x3 + bc * x3l;
-        const V h3u = ac * x3u + bc * x3ul;
-        x0 += c * (ac * x1 + bc * x1l) + c * (ar * x2 + br * x2u) + cc * (ar * h3 + br * h3u);
-        x1 += c * (ar * x3 + br * x3u);
-        x2 += c * h3;
+        const V h3 = fmaf(bc, x3l, ac * x3);
+        const V h3u = fmaf(bc, x3ul, ac * x3u);
+        x0 = fmaf(cc, fmaf(br, h3u, ar * h3),
+                  fmaf(c, fmaf(br, x2u, ar * x2), fmaf(c, fmaf(bc, x1l, ac * x1), x0)));
+        x1 = fmaf(c, fmaf(br, x3u, ar * x3), x1);
+        x2 = fmaf(c, h3, x2);
     } else {
         // Symmetric extension in the polyphase domain: a neighbour index -1
         // reads index 0 and an index past the end of a component reads its
@@ -228,13 +230,14 @@ __device__ __forceinline__ void minus_block(V& x0, V& x1, V& x2, V& x3,
         const V x2uc = rU ? x2u : x2;         // x2 at (n-1, m) clamped
         if constexpr (KIND == kFloat) {
             const float cc = c * c;
-            x0 += c * (x1lc + x1o) + c * (x2uc + x2o) + cc * ((X3oo + X3ol) + (X3uo + X3ul));
-            x1 += c * (X3oo + X3uo);
-            x2 += c * (X3oo + X3ol);
+            const V s3 = (X3oo + X3ol) + (X3uo + X3ul);
+            x0 = fmaf(cc, s3, fmaf(c, x2uc + x2o, fmaf(c, x1lc + x1o, x0)));
+            x1 = fmaf(c, X3oo + X3uo, x1);
+            x2 = fmaf(c, X3oo + X3ol, x2);
         } else if constexpr (KIND == kSplit) {
-            x0 += c * x1lc + c * x2uc + (c * c) * X3ul;
-            x1 += c * X3uo;
-            x2 += c * X3ol;
+            x0 = fmaf(c * c, X3ul, fmaf(c, x2uc, fmaf(c, x1lc, x0)));
+            x1 = fmaf(c, X3uo, x1);
+            x2 = fmaf(c, X3ol, x2);
         } else if constexpr (KIND == kIntFwd) {
             // S^H then S^V; x2 after S^H in the row above is recomputed.
             const V x2h_own = x2 + ((x3o + x3lc + 2) >> 2);
@@ -264,11 +267,11 @@ __device__ __forceinline__ void minus_block(V& x0, V& x1, V& x2, V& x3,
 // ---------------------------------------------------------------------------
 template <typename V> using Row8 = V[8];
 
-template <typename V>
+template <int K, typename V>
 __device__ __forceinline__ void publish_top(V (&a)[K][8], Vec4<V> (*buf)[kLanes], int lane, int wv) {
     buf[wv][lane] = Vec4<V>{a[0][0], a[0][1], a[0][4], a[0][5]};
 }
-template <typename V>
+template <int K, typename V>
 __device__ __forceinline__ void publish_bottom(V (&a)[K][8], Vec4<V> (*buf)[kLanes], int lane, int wv) {
     buf[wv][lane] = Vec4<V>{a[K - 1][2], a[K - 1][3], a[K - 1][6], a[K - 1][7]};
 }
@@ -276,7 +279,7 @@ __device__ __forceinline__ void publish_bottom(V (&a)[K][8], Vec4<V> (*buf)[kLan
 // Predict-shaped step over the tile: every block reads x0/x1/x2 of its right,
 // lower and lower-right neighbours as they were before the step.  Rows are
 // visited top to bottom so row r+1 is still unmodified when row r reads it.
-template <int KIND, bool EDGE, typename V>
+template <int KIND, bool EDGE, int NW, int K, typename V>
 __device__ __forceinline__ void plus_step(V (&a)[K][8], Vec4<V> (*buf)[kLanes], int lane, int wv,
                                           const Geo& g, float c) {
     V rrow = from_right(a[0][0]);                 // right lane's L.x0, row r
@@ -306,7 +309,7 @@ __device__ __forceinline__ void plus_step(V (&a)[K][8], Vec4<V> (*buf)[kLanes], 
 // Update-shaped step: every block reads x1/x2/x3 of its left, upper and
 // upper-left neighbours as they were before the step.  Rows are visited bottom
 // to top; within a row the R block goes first because it reads the L block.
-template <int KIND, bool EDGE, typename V>
+template <int KIND, bool EDGE, int NW, int K, typename V>
 __device__ __forceinline__ void minus_step(V (&a)[K][8], Vec4<V> (*buf)[kLanes], int lane, int wv,
                                            const Geo& g, float c) {
     V lrow = from_left(a[K - 1][7]);              // left lane's R.x3, row r
@@ -335,31 +338,31 @@ __device__ __forceinline__ void minus_step(V (&a)[K][8], Vec4<V> (*buf)[kLanes],
 
 // Constant parts of the split (no neighbour access): separable lifting with
 // P0 = c (horizontal, then vertical) and with U0 = c.
-template <typename V>
+template <int K, typename V>
 __device__ __forceinline__ void local_predict(V (&a)[K][8], float c) {
 #pragma unroll
     for (int r = 0; r < K; ++r)
 #pragma unroll
         for (int b = 0; b < 8; b += 4) {
-            a[r][b + 1] += c * a[r][b + 0];
-            a[r][b + 3] += c * a[r][b + 2];
-            a[r][b + 2] += c * a[r][b + 0];
-            a[r][b + 3] += c * a[r][b + 1];
+            a[r][b + 1] = fmaf(c, a[r][b + 0], a[r][b + 1]);
+            a[r][b + 3] = fmaf(c, a[r][b + 2], a[r][b + 3]);
+            a[r][b + 2] = fmaf(c, a[r][b + 0], a[r][b + 2]);
+            a[r][b + 3] = fmaf(c, a[r][b + 1], a[r][b + 3]);
         }
 }
-template <typename V>
+template <int K, typename V>
 __device__ __forceinline__ void local_update(V (&a)[K][8], float c) {
 #pragma unroll
     for (int r = 0; r < K; ++r)
 #pragma unroll
         for (int b = 0; b < 8; b += 4) {
-            a[r][b + 0] += c * a[r][b + 1];
-            a[r][b + 2] += c * a[r][b + 3];
-            a[r][b + 0] += c * a[r][b + 2];
-            a[r][b + 1] += c * a[r][b + 3];
+            a[r][b + 0] = fmaf(c, a[r][b + 1], a[r][b + 0]);
+            a[r][b + 2] = fmaf(c, a[r][b + 3], a[r][b + 2]);
+            a[r][b + 0] = fmaf(c, a[r][b + 2], a[r][b + 0]);
+            a[r][b + 1] = fmaf(c, a[r][b + 3], a[r][b + 1]);
         }
 }
-template <typename V>
+template <int K, typename V>
 __device__ __forceinline__ void scale(V (&a)[K][8], float s0, float s3) {
 #pragma unroll
     for (int r = 0; r < K; ++r) {
@@ -370,13 +373,13 @@ __device__ __forceinline__ void scale(V (&a)[K][8], float s0, float s3) {
 
 // The step program of one scale.  Each "sync" is the single barrier of one
 // fused step; the LDS edge row it guards is published just before it.
-template <int DIR, int WAV, bool EDGE, bool SPLIT, typename V>
+template <int DIR, int WAV, bool EDGE, bool SPLIT, int NW, int K, typename V>
 __device__ __forceinline__ void run(V (&a)[K][8], Vec4<V> (*bT)[kLanes], Vec4<V> (*bS)[kLanes],
                                     int lane, int wv, const Geo& g) {
 #define DWT2_PLUS(KIND_, c_) publish_top(a, bT, lane, wv); __syncthreads(); \
-    plus_step<KIND_, EDGE>(a, bT, lane, wv, g, (c_));
+    plus_step<KIND_, EDGE, NW>(a, bT, lane, wv, g, (c_));
 #define DWT2_MINUS(KIND_, c_) publish_bottom(a, bS, lane, wv); __syncthreads(); \
-    minus_step<KIND_, EDGE>(a, bS, lane, wv, g, (c_));
+    minus_step<KIND_, EDGE, NW>(a, bS, lane, wv, g, (c_));
     if constexpr (WAV == kCdf53) {
         if constexpr (DIR == kForward) {
             DWT2_PLUS(kIntFwd, 0.f)
@@ -503,7 +506,7 @@ __device__ __forceinline__ void store2(T* rowp, int gc, int ncols, bool vec,
 }
 
 // Load the tile (halo included) into registers.
-template <int DIR, typename T, bool EDGE>
+template <int DIR, typename T, bool EDGE, int K>
 __device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][8], const LevelParams& P, const Geo& g) {
     const bool vec = P.vec != 0;
     if constexpr (DIR == kForward) {
@@ -533,9 +536,10 @@ __device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][8], const Le
 }
 
 // Store the core of the tile (halo lanes and rows dropped).
-template <int DIR, typename T, bool EDGE>
+template <int DIR, typename T, bool EDGE, int NW, int K>
 __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][8], const LevelParams& P,
                                            const Geo& g, int lane, int wv) {
+    constexpr int kCoreBY = NW * K - 2 * kHalo;
     if (lane < kHalo / 2 || lane >= kLanes - kHalo / 2) return;
     const bool vec = P.vec != 0;
 #pragma unroll
@@ -563,13 +567,15 @@ __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][8], const L
     }
 }
 
-template <int DIR, int WAV, typename T, bool SPLIT>
+template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K>
 __global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
     using V = typename St<T>::V;
+    constexpr int kCoreBY = NW * K - 2 * kHalo;
     __shared__ Vec4<V> bufT[NW][kLanes];
     __shared__ Vec4<V> bufS[NW][kLanes];
     const int lane = threadIdx.x & (kLanes - 1);
-    const int wv = threadIdx.x / kLanes;
+    // the wave index is uniform: keep it (and every row address) in SGPRs
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
 
     // Work-groups are dealt round-robin over the 8 XCDs; give each XCD a
     // contiguous run of tiles (row-major) so neighbouring halos share its L2.
@@ -593,55 +599,69 @@ __global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
     V a[K][8];
     if (interior) {
         load_tile<DIR, T, false>(a, P, g);
-        run<DIR, WAV, false, SPLIT>(a, bufT, bufS, lane, wv, g);
-        store_tile<DIR, T, false>(a, P, g, lane, wv);
+        run<DIR, WAV, false, SPLIT, NW>(a, bufT, bufS, lane, wv, g);
+        store_tile<DIR, T, false, NW>(a, P, g, lane, wv);
     } else {
         load_tile<DIR, T, true>(a, P, g);
-        run<DIR, WAV, true, false>(a, bufT, bufS, lane, wv, g);
-        store_tile<DIR, T, true>(a, P, g, lane, wv);
+        run<DIR, WAV, true, false, NW>(a, bufT, bufS, lane, wv, g);
+        store_tile<DIR, T, true, NW>(a, P, g, lane, wv);
     }
 }
 
-template <int DIR, int WAV, typename T, bool SPLIT>
-hipError_t launch(const LevelParams& p, hipStream_t s) {
+template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K>
+hipError_t launch_shape(const LevelParams& p, hipStream_t s) {
     const int nt = p.tiles_x * p.tiles_y;
     const int grid = ((nt + 7) >> 3) * 8;
-    hipLaunchKernelGGL((level_kernel<DIR, WAV, T, SPLIT>), dim3(grid), dim3(NW * kLanes), 0, s, p);
+    hipLaunchKernelGGL((level_kernel<DIR, WAV, T, SPLIT, NW, K>), dim3(grid), dim3(NW * kLanes), 0, s, p);
     return hipGetLastError();
 }
 
+template <int DIR, int WAV, typename T, bool SPLIT>
+hipError_t launch(int shape, const LevelParams& p, hipStream_t s) {
+    static_assert(kNumTileShapes == 6, "dispatch table below lists every tile shape");
+    switch (shape) {
+        case 0: return launch_shape<DIR, WAV, T, SPLIT, kTileShapes[0].waves, kTileShapes[0].rows>(p, s);
+        case 1: return launch_shape<DIR, WAV, T, SPLIT, kTileShapes[1].waves, kTileShapes[1].rows>(p, s);
+        case 2: return launch_shape<DIR, WAV, T, SPLIT, kTileShapes[2].waves, kTileShapes[2].rows>(p, s);
+        case 3: return launch_shape<DIR, WAV, T, SPLIT, kTileShapes[3].waves, kTileShapes[3].rows>(p, s);
+        case 4: return launch_shape<DIR, WAV, T, SPLIT, kTileShapes[4].waves, kTileShapes[4].rows>(p, s);
+        case 5: return launch_shape<DIR, WAV, T, SPLIT, kTileShapes[5].waves, kTileShapes[5].rows>(p, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <int DIR, typename T>
-hipError_t launch_float(bool split, const LevelParams& p, hipStream_t s) {
+hipError_t launch_float(bool split, int shape, const LevelParams& p, hipStream_t s) {
     if constexpr (DIR == kAdjoint) {
-        return launch<DIR, kCdf97, T, false>(p, s);
+        return launch<DIR, kCdf97, T, false>(shape, p, s);
     } else {
-        return split ? launch<DIR, kCdf97, T, true>(p, s) : launch<DIR, kCdf97, T, false>(p, s);
+        return split ? launch<DIR, kCdf97, T, true>(shape, p, s) : launch<DIR, kCdf97, T, false>(shape, p, s);
     }
 }
 
 template <int DIR>
-hipError_t launch_dir(Wavelet wav, Dtype dt, bool split, const LevelParams& p, hipStream_t s) {
+hipError_t launch_dir(Wavelet wav, Dtype dt, bool split, int shape, const LevelParams& p, hipStream_t s) {
     if (wav == kCdf53) {
         if constexpr (DIR == kAdjoint) return hipErrorInvalidValue;
-        else return launch<DIR, kCdf53, int32_t, false>(p, s);
+        else return launch<DIR, kCdf53, int32_t, false>(shape, p, s);
     }
     switch (dt) {
-        case kF32: return launch_float<DIR, float>(split, p, s);
-        case kBF16: return launch_float<DIR, __hip_bfloat16>(split, p, s);
-        case kF16: return launch_float<DIR, __half>(split, p, s);
+        case kF32: return launch_float<DIR, float>(split, shape, p, s);
+        case kBF16: return launch_float<DIR, __hip_bfloat16>(split, shape, p, s);
+        case kF16: return launch_float<DIR, __half>(split, shape, p, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t launch_level(Direction dir, Wavelet wav, Dtype dt, bool split,
+hipError_t launch_level(Direction dir, Wavelet wav, Dtype dt, bool split, int shape,
                         const LevelParams& p, hipStream_t stream) {
     if (p.tiles_x <= 0 || p.tiles_y <= 0) return hipSuccess;
     switch (dir) {
-        case kForward: return launch_dir<kForward>(wav, dt, split, p, stream);
-        case kInverse: return launch_dir<kInverse>(wav, dt, split, p, stream);
-        case kAdjoint: return launch_dir<kAdjoint>(wav, dt, split, p, stream);
+        case kForward: return launch_dir<kForward>(wav, dt, split, shape, p, stream);
+        case kInverse: return launch_dir<kInverse>(wav, dt, split, shape, p, stream);
+        case kAdjoint: return launch_dir<kAdjoint>(wav, dt, split, shape, p, stream);
     }
     return hipErrorInvalidValue;
 }
