@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-forms", action="store_true", help="skip the secondary forms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="also run a plain 256 MiB device copy (torch copy_) a few times, as the "
+                         "known-size reference for hardware byte counters")
     return ap.parse_args()
 
 
@@ -154,6 +157,14 @@ def main():
         form("cdf53 inv i32 1 level", lambda i: d.inv(yi[i % pairs], "cdf53", 1, out=xi[i % pairs]), 1, 4)
         del xi, yi
 
+    copy_ref = None
+    if args.copy_reference:
+        # a plain copy of one input to one output buffer: reads and writes N*N*4 bytes
+        _, per_c = time_steps(torch, lambda i: ys[i % pairs].copy_(xs[i % pairs]), 10, 2)
+        cms = float(np.median(per_c))
+        copy_ref = {"bytes_per_launch": 2 * N * N * 4, "median_ms": round(cms, 5),
+                    "GB/s": round(2 * N * N * 4 / (cms * 1e-3) / 1e9, 1)}
+
     cpu = None if args.no_cpu else cpu_baseline(x_host, args.cpu_seconds)
 
     line = {
@@ -176,6 +187,8 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
     }
+    if copy_ref is not None:
+        line["copy_reference"] = copy_ref
     print(json.dumps(line), flush=True)
 
 

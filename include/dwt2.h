@@ -91,13 +91,20 @@ typedef enum {
                                 (Section "Optimization Approach"); CDF 9/7 only.
                                 Same values up to FP32 rounding; applied in tiles
                                 away from the image border.                    */
-/* Tile shape: bits 8..15 hold 1 + the index of a shape listed by
- * dwt2_tile_shape(); 0 selects the library default.  Every shape computes the
- * same values (bit-identical for the same flags otherwise). */
-#define DWT2_FLAG_TILE_SHIFT 8
-#define DWT2_FLAG_TILE_MASK 0xff00u
-#define DWT2_FLAG_TILE(i) (((unsigned)(i) + 1u) << DWT2_FLAG_TILE_SHIFT)
-#define DWT2_NUM_TILE_SHAPES 6
+/* Kernel configuration: bits 8..15 hold 1 + the index of a configuration
+ * listed by dwt2_kernel_config(); 0 selects the library default.  Every
+ * configuration computes the same values (bit-identical for the same other
+ * flags); they differ only in how the work is laid out on the GPU. */
+#define DWT2_FLAG_KERNEL_SHIFT 8
+#define DWT2_FLAG_KERNEL_MASK 0xff00u
+#define DWT2_FLAG_KERNEL(i) (((unsigned)(i) + 1u) << DWT2_FLAG_KERNEL_SHIFT)
+#define DWT2_NUM_KERNEL_CONFIGS 8
+
+/* Kernel algorithms (dwt2_kernel_config). */
+#define DWT2_ALGO_TILE 0     /* work-group tile in VGPRs, waves stacked
+                                vertically, one LDS barrier per fused step */
+#define DWT2_ALGO_STREAM 1   /* each wave64 walks down a column strip with a
+                                register window; no LDS, no barrier */
 
 /* One image of a batched call.  Pitches in elements. */
 typedef struct {
@@ -141,18 +148,46 @@ int dwt2_inv(const void* src, void* dst, int32_t height, int32_t width,
  * W^T src in image layout.  The transposed fused steps run in reverse order,
  * coarsest level first; at the borders the transposes of the symmetric
  * extension are used (they are not a symmetric extension).  CDF 9/7 only;
- * flags must be 0. */
+ * DWT2_FLAG_SPLIT is not accepted. */
 int dwt2_adj(const void* src, void* dst, int32_t height, int32_t width,
              int64_t src_pitch, int64_t dst_pitch, dwt2_dtype dtype,
              dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,
              unsigned flags, void* workspace, size_t workspace_bytes,
              void* stream);
 
-/* Describe tile shape `index` (0 .. DWT2_NUM_TILE_SHAPES-1): wave64s per
- * work-group, block rows held per lane, and the core (output) size of one tile
- * in 2x2-pixel blocks.  Any output pointer may be NULL.  Returns DWT2_OK or
- * DWT2_E_FLAGS for an unknown index. */
-int dwt2_tile_shape(int index, int* waves, int* rows_per_lane, int* core_cols, int* core_rows);
+/* Describe kernel configuration `index` (0 .. DWT2_NUM_KERNEL_CONFIGS-1):
+ * algorithm (DWT2_ALGO_*), wave64s per work-group, block rows per lane
+ * (tile) or rows of loads in flight (stream), and the output size one
+ * work-group tile (or one wave segment) covers in 2x2-pixel blocks: core_cols
+ * columns by core_rows rows.  Any output pointer may be NULL.  Returns
+ * DWT2_OK or DWT2_E_FLAGS for an unknown index. */
+int dwt2_kernel_config(int index, int* algorithm, int* waves, int* rows, int* core_cols, int* core_rows);
+
+/* Device workspace (bytes) for dwt2_fwd_batched on these images: a work
+ * table and two LL ping-pong buffers per image.  `images` is a host array. */
+int dwt2_workspace_bytes_batched(const dwt2_image* images, int count, dwt2_dtype dtype, int levels,
+                                 size_t* bytes);
+
+/* Batched forward CDF 9/7: `count` independent images of any (uneven) sizes,
+ * every one transformed to `levels` levels, in one planner launch plus one
+ * persistent launch on `stream` (each work-group takes tiles of any image and
+ * level from a device work queue; a level waits only for the previous level
+ * of the same image).  The images are given twice with identical contents:
+ * `host_images` (host memory, used for the argument checks and the grid) and
+ * `device_images` (device memory, read by the kernels), so the call performs
+ * no copies or allocations and can be captured in a graph.  Float storage
+ * (F32, BF16, F16); flags: DWT2_FLAG_SPLIT and a tile kernel configuration
+ * (indices 0 or 1 of dwt2_kernel_config).  Every image's src and dst must not
+ * overlap each other or the workspace.  Results equal dwt2_fwd on each image
+ * (bit-identical for the same configuration). */
+int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_images, int count,
+                     dwt2_dtype dtype, dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,
+                     unsigned flags, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Error word of a batched call's workspace header, read from a host copy of
+ * the workspace's first 64 bytes: non-zero if a dependency wait gave up (the
+ * results are then not valid).  Returns the word, or DWT2_E_NULL. */
+int dwt2_batched_error(const void* workspace_host_copy);
 
 /* Text of a dwt2_status. */
 const char* dwt2_status_string(int status);

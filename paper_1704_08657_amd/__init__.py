@@ -27,12 +27,14 @@ DWT2_CDF97, DWT2_CDF53_REV = 0, 1
 DWT2_F32, DWT2_BF16, DWT2_F16, DWT2_I32 = 0, 1, 2, 3
 DWT2_SYMMETRIC_WHOLE = 0
 DWT2_FLAG_SPLIT = 1
-DWT2_FLAG_TILE_SHIFT = 8
-DWT2_NUM_TILE_SHAPES = 6
+DWT2_FLAG_KERNEL_SHIFT = 8
+DWT2_NUM_KERNEL_CONFIGS = 8
+DWT2_ALGO_TILE, DWT2_ALGO_STREAM = 0, 1
 
 
-def DWT2_FLAG_TILE(i: int) -> int:
-    return (i + 1) << DWT2_FLAG_TILE_SHIFT
+def DWT2_FLAG_KERNEL(i: int) -> int:
+    return (i + 1) << DWT2_FLAG_KERNEL_SHIFT
+
 
 WAVELETS = {"cdf97": DWT2_CDF97, "cdf53": DWT2_CDF53_REV}
 
@@ -47,7 +49,10 @@ SIGNATURES = {
     "dwt2_fwd": (_c_int, _TRANSFORM_ARGS),
     "dwt2_inv": (_c_int, _TRANSFORM_ARGS),
     "dwt2_adj": (_c_int, _TRANSFORM_ARGS),
-    "dwt2_tile_shape": (_c_int, [_c_int] + [ctypes.POINTER(_c_int)] * 4),
+    "dwt2_kernel_config": (_c_int, [_c_int] + [ctypes.POINTER(_c_int)] * 5),
+    "dwt2_workspace_bytes_batched": (_c_int, [_c_p, _c_int, _c_int, _c_int, ctypes.POINTER(_c_sz)]),
+    "dwt2_fwd_batched": (_c_int, [_c_p, _c_p, _c_int, _c_int, _c_int, _c_int, _c_int, _c_u, _c_p, _c_sz, _c_p]),
+    "dwt2_batched_error": (_c_int, [_c_p]),
     "dwt2_status_string": (ctypes.c_char_p, [_c_int]),
     "dwt2_last_hip_error": (ctypes.c_char_p, []),
 }
@@ -104,10 +109,10 @@ def dwt2_adj(*args) -> int:
     return lib().dwt2_adj(*args)
 
 
-def dwt2_tile_shape(index: int):
-    """(status, waves, rows_per_lane, core_cols, core_rows) of a tile shape."""
-    v = [ctypes.c_int(0) for _ in range(4)]
-    st = lib().dwt2_tile_shape(index, *[ctypes.byref(x) for x in v])
+def dwt2_kernel_config(index: int):
+    """(status, algorithm, waves, rows, core_cols, core_rows) of a kernel configuration."""
+    v = [ctypes.c_int(0) for _ in range(5)]
+    st = lib().dwt2_kernel_config(index, *[ctypes.byref(x) for x in v])
     return (st, *[x.value for x in v])
 
 
@@ -156,7 +161,7 @@ def workspace(h: int, w: int, levels: int, dtype, device):
     return torch.empty(n, dtype=torch.uint8, device=device)
 
 
-def _transform(fn, name, x, wavelet, levels, split, out, tile=None):
+def _transform(fn, name, x, wavelet, levels, split, out, config=None):
     torch = _torch()
     _check(x)
     x2 = x.reshape(-1, *x.shape[-2:]) if x.is_contiguous() else x.contiguous().reshape(-1, *x.shape[-2:])
@@ -174,8 +179,8 @@ def _transform(fn, name, x, wavelet, levels, split, out, tile=None):
     ws_n = ws.numel() if ws is not None else 0
     stream = _stream_ptr(x2)
     flags = DWT2_FLAG_SPLIT if split else 0
-    if tile is not None:
-        flags |= DWT2_FLAG_TILE(tile)
+    if config is not None:
+        flags |= DWT2_FLAG_KERNEL(config)
     for i in range(x2.shape[0]):
         st = fn(ctypes.c_void_p(x2[i].data_ptr()), ctypes.c_void_p(out[i].data_ptr()), H, W,
                 x2.stride(-2), out.stride(-2), dt, WAVELETS[wavelet], levels,
@@ -185,20 +190,83 @@ def _transform(fn, name, x, wavelet, levels, split, out, tile=None):
     return out.reshape(x.shape)
 
 
-def fwd(x, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, tile=None):
+def fwd(x, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None):
     """Forward transform of every [H, W] plane of x into a Mallat pyramid.
-    `tile` selects a tile shape index (None: library default)."""
-    return _transform(dwt2_fwd, "dwt2_fwd", x, wavelet, levels, split, out, tile)
+    `config` selects a kernel configuration index (None: library default)."""
+    return _transform(dwt2_fwd, "dwt2_fwd", x, wavelet, levels, split, out, config)
 
 
-def inv(c, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, tile=None):
+def inv(c, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None):
     """Inverse transform of every [H, W] Mallat pyramid of c."""
-    return _transform(dwt2_inv, "dwt2_inv", c, wavelet, levels, split, out, tile)
+    return _transform(dwt2_inv, "dwt2_inv", c, wavelet, levels, split, out, config)
 
 
-def adj(g, levels: int = 1, out=None, tile=None):
+def adj(g, levels: int = 1, out=None, config=None):
     """Adjoint W^T g of the CDF 9/7 forward transform (cotangent in Mallat layout)."""
-    return _transform(dwt2_adj, "dwt2_adj", g, "cdf97", levels, False, out, tile)
+    return _transform(dwt2_adj, "dwt2_adj", g, "cdf97", levels, False, out, config)
+
+
+class dwt2_image(ctypes.Structure):
+    """The C struct dwt2_image."""
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("height", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("src_pitch", ctypes.c_int64), ("dst_pitch", ctypes.c_int64)]
+
+
+class BatchedForward:
+    """One batched forward CDF 9/7 call over a list of [H, W] images.
+
+    Holds the host and device descriptor arrays and the workspace, so that
+    `run()` can be called repeatedly (or captured in a graph); `outs` are the
+    Mallat pyramids, one per image."""
+
+    def __init__(self, images, levels: int, split: bool = False, config=None, outs=None):
+        torch = _torch()
+        if not images:
+            raise ValueError("empty batch")
+        for x in images:
+            _check(x)
+            if x.dim() != 2 or not x.is_contiguous():
+                raise ValueError("every image must be a contiguous [H, W] tensor")
+            if x.dtype != images[0].dtype or x.device != images[0].device:
+                raise ValueError("images must share dtype and device")
+        self.images = list(images)
+        self.outs = list(outs) if outs is not None else [torch.empty_like(x) for x in images]
+        self.levels = levels
+        self.dtype = dtype_code(images[0])
+        self.flags = (DWT2_FLAG_SPLIT if split else 0) | (DWT2_FLAG_KERNEL(config) if config is not None else 0)
+        n = len(images)
+        self.host = (dwt2_image * n)()
+        for i, (x, y) in enumerate(zip(self.images, self.outs)):
+            self.host[i] = dwt2_image(x.data_ptr(), y.data_ptr(), x.shape[0], x.shape[1], x.stride(0), y.stride(0))
+        raw = bytes(self.host)
+        self.device = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(images[0].device)
+        nbytes = ctypes.c_size_t(0)
+        st = lib().dwt2_workspace_bytes_batched(ctypes.cast(self.host, ctypes.c_void_p), n, self.dtype, levels,
+                                                ctypes.byref(nbytes))
+        if st != DWT2_OK:
+            raise DWT2Error(st, "dwt2_workspace_bytes_batched")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=images[0].device)
+
+    def run(self):
+        st = lib().dwt2_fwd_batched(ctypes.cast(self.host, ctypes.c_void_p), ctypes.c_void_p(self.device.data_ptr()),
+                                    len(self.images), self.dtype, DWT2_CDF97, self.levels, DWT2_SYMMETRIC_WHOLE,
+                                    self.flags, ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                    _stream_ptr(self.images[0]))
+        if st != DWT2_OK:
+            raise DWT2Error(st, "dwt2_fwd_batched")
+        return self.outs
+
+    def error_word(self) -> int:
+        """Non-zero if a dependency wait of the last run gave up (synchronises)."""
+        head = self.workspace[:64].cpu().numpy().tobytes()
+        buf = ctypes.create_string_buffer(head, 64)
+        return lib().dwt2_batched_error(ctypes.cast(buf, ctypes.c_void_p))
+
+
+def fwd_batched(images, levels: int = 1, split: bool = False, config=None, outs=None):
+    """Forward CDF 9/7 of a list of [H, W] images of any sizes in one
+    persistent launch; returns the list of Mallat pyramids."""
+    return BatchedForward(images, levels, split, config, outs).run()
 
 
 def _make_function():

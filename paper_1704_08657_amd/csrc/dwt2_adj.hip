@@ -1,0 +1,10 @@
+// Kernels and launch of one direction (kAdjoint); see dwt2_kernels.inl.
+#include "dwt2_launch.inl"
+
+namespace dwt2 {
+
+hipError_t launch_adj(Wavelet wav, Dtype dt, bool split, int cfg, const LevelParams& p, hipStream_t s) {
+    return kern::launch_dir<kAdjoint>(wav, dt, split, cfg, p, s);
+}
+
+}  // namespace dwt2

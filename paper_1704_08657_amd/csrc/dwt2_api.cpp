@@ -8,10 +8,11 @@
 
 #include <string>
 
-#include "../../include/dwt2.h"
+#include "dwt2.h"
+#include "dwt2_batch_plan.h"
 #include "dwt2_internal.h"
 
-static_assert(DWT2_NUM_TILE_SHAPES == dwt2::kNumTileShapes, "tile shape count in dwt2.h");
+static_assert(DWT2_NUM_KERNEL_CONFIGS == dwt2::kNumConfigs, "kernel configuration count in dwt2.h");
 
 namespace {
 
@@ -93,8 +94,8 @@ int validate(const void* src, void* dst, int32_t h, int32_t w, int64_t sp, int64
         return DWT2_E_DTYPE;
     if ((wavelet == DWT2_CDF53_REV) != (dtype == DWT2_I32)) return DWT2_E_DTYPE;
     if (boundary != DWT2_SYMMETRIC_WHOLE) return DWT2_E_BOUNDARY;
-    if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_TILE_MASK)) return DWT2_E_FLAGS;
-    if (((flags & DWT2_FLAG_TILE_MASK) >> DWT2_FLAG_TILE_SHIFT) > (unsigned)dwt2::kNumTileShapes)
+    if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_KERNEL_MASK)) return DWT2_E_FLAGS;
+    if (((flags & DWT2_FLAG_KERNEL_MASK) >> DWT2_FLAG_KERNEL_SHIFT) > (unsigned)dwt2::kNumConfigs)
         return DWT2_E_FLAGS;
     if ((flags & DWT2_FLAG_SPLIT) && (wavelet != DWT2_CDF97 || adjoint)) return DWT2_E_FLAGS;
     if (adjoint && wavelet != DWT2_CDF97) return DWT2_E_WAVELET;
@@ -123,17 +124,27 @@ int report(hipError_t e) {
 dwt2::Dtype to_dtype(int d) { return (dwt2::Dtype)d; }
 dwt2::Wavelet to_wav(int w) { return w == DWT2_CDF97 ? dwt2::kCdf97 : dwt2::kCdf53; }
 
-void tiles(int shape, int32_t h, int32_t w, int32_t* tx, int32_t* ty) {
-    const int32_t nEr = (h + 1) / 2, nEc = (w + 1) / 2;
-    const int cy = dwt2::core_rows(dwt2::kTileShapes[shape]);
-    *tx = (nEc + dwt2::kCoreBX - 1) / dwt2::kCoreBX;
-    *ty = (nEr + cy - 1) / cy;
+// Work-group grid of one level for kernel configuration `cfg`.
+void plan_grid(int cfg, dwt2::LevelParams* lp) {
+    const dwt2::KernelConfig c = dwt2::kConfigs[cfg];
+    const int32_t nEr = (lp->h + 1) / 2, nEc = (lp->w + 1) / 2;
+    if (c.algo == dwt2::kAlgoTile) {
+        const int cy = dwt2::core_rows(c);
+        lp->tiles_x = (nEc + dwt2::kTileCoreBX - 1) / dwt2::kTileCoreBX;
+        lp->tiles_y = (nEr + cy - 1) / cy;
+        lp->seg_rows = 0;
+    } else {
+        const int32_t strips = (nEc + dwt2::kStreamCoreBX - 1) / dwt2::kStreamCoreBX;
+        lp->tiles_x = (strips + c.waves - 1) / c.waves;
+        lp->tiles_y = (nEr + c.seg - 1) / c.seg;
+        lp->seg_rows = c.seg;
+    }
 }
 
-// Tile shape selected by the flags (0 in the tile field = library default).
-int shape_of(unsigned flags) {
-    const unsigned t = (flags >> DWT2_FLAG_TILE_SHIFT) & 0xffu;
-    return t == 0 ? dwt2::kDefaultTileShape : (int)t - 1;
+// Kernel configuration selected by the flags (0 in the field = default).
+int config_of(unsigned flags) {
+    const unsigned t = (flags & DWT2_FLAG_KERNEL_MASK) >> DWT2_FLAG_KERNEL_SHIFT;
+    return t == 0 ? dwt2::kDefaultConfig : (int)t - 1;
 }
 
 // Forward: level l reads the LL of level l-1 (src for l = 0) and writes its
@@ -161,13 +172,13 @@ int run_forward(const void* src, void* dst, int32_t h, int32_t w, int64_t sp, in
         const bool last = l + 1 == levels;
         lp.out_ll = last ? dst : (void*)bufs[l % 2];
         lp.out_ll_pitch = last ? dp : ws_pitch((lp.w + 1) / 2);
-        tiles(shape_of(flags), lp.h, lp.w, &lp.tiles_x, &lp.tiles_y);
+        plan_grid(config_of(flags), &lp);
         const int32_t nEc = (lp.w + 1) / 2;
         lp.vec = aligned(lp.in, 4 * es) && lp.in_pitch % 4 == 0 &&
                  aligned(lp.out, 2 * es) && lp.out_pitch % 2 == 0 && nEc % 2 == 0 &&
                  aligned(lp.out_ll, 2 * es) && lp.out_ll_pitch % 2 == 0;
         const int rc = report(dwt2::launch_level(dwt2::kForward, to_wav(wavelet), to_dtype(dtype),
-                                                 (flags & DWT2_FLAG_SPLIT) != 0, shape_of(flags), lp, s));
+                                                 (flags & DWT2_FLAG_SPLIT) != 0, config_of(flags), lp, s));
         if (rc) return rc;
         in = lp.out_ll;
         in_pitch = lp.out_ll_pitch;
@@ -200,13 +211,13 @@ int run_backward(dwt2::Direction dir, const void* src, void* dst, int32_t h, int
         // the image of level l is the LL of level l-1 (kept in buffer (l-1) % 2)
         lp.out = l == 0 ? dst : (void*)bufs[(l - 1) % 2];
         lp.out_pitch = l == 0 ? dp : ws_pitch(lp.w);
-        tiles(shape_of(flags), lp.h, lp.w, &lp.tiles_x, &lp.tiles_y);
+        plan_grid(config_of(flags), &lp);
         const int32_t nEc = (lp.w + 1) / 2;
         lp.vec = aligned(lp.in, 2 * es) && lp.in_pitch % 2 == 0 && nEc % 2 == 0 &&
                  aligned(lp.in_ll, 2 * es) && lp.in_ll_pitch % 2 == 0 &&
                  aligned(lp.out, 4 * es) && lp.out_pitch % 4 == 0;
         const int rc = report(dwt2::launch_level(dir, to_wav(wavelet), to_dtype(dtype),
-                                                 (flags & DWT2_FLAG_SPLIT) != 0, shape_of(flags), lp, s));
+                                                 (flags & DWT2_FLAG_SPLIT) != 0, config_of(flags), lp, s));
         if (rc) return rc;
         ll = lp.out;
         ll_pitch = lp.out_pitch;
@@ -269,14 +280,82 @@ int dwt2_adj(const void* src, void* dst, int32_t height, int32_t width, int64_t 
                         wavelet, levels, flags, workspace, (hipStream_t)stream);
 }
 
-int dwt2_tile_shape(int index, int* waves, int* rows_per_lane, int* core_cols, int* core_rows) {
-    if (index < 0 || index >= dwt2::kNumTileShapes) return DWT2_E_FLAGS;
-    const dwt2::TileShape t = dwt2::kTileShapes[index];
-    if (waves) *waves = t.waves;
-    if (rows_per_lane) *rows_per_lane = t.rows;
-    if (core_cols) *core_cols = dwt2::kCoreBX;
-    if (core_rows) *core_rows = dwt2::core_rows(t);
+int dwt2_kernel_config(int index, int* algorithm, int* waves, int* rows, int* core_cols, int* core_rows) {
+    if (index < 0 || index >= dwt2::kNumConfigs) return DWT2_E_FLAGS;
+    const dwt2::KernelConfig c = dwt2::kConfigs[index];
+    if (algorithm) *algorithm = c.algo;
+    if (waves) *waves = c.waves;
+    if (rows) *rows = c.rows;
+    if (core_cols) *core_cols = c.algo == dwt2::kAlgoTile ? dwt2::kTileCoreBX : dwt2::kStreamCoreBX;
+    if (core_rows) *core_rows = c.algo == dwt2::kAlgoTile ? dwt2::core_rows(c) : c.seg;
     return DWT2_OK;
+}
+
+int dwt2_workspace_bytes_batched(const dwt2_image* images, int count, dwt2_dtype dtype, int levels,
+                                 size_t* bytes) {
+    if (!bytes || !images) return DWT2_E_NULL;
+    *bytes = 0;
+    if (count < 1) return DWT2_E_COUNT;
+    const size_t es = elem_size(dtype);
+    if (!es) return DWT2_E_DTYPE;
+    const dwt2::BatchLayout L = dwt2::batch_layout(count, levels < 1 ? 1 : levels);
+    size_t total = L.off_ll;
+    for (int i = 0; i < count; ++i) {
+        const dwt2_image& im = images[i];
+        if (im.height < 2 || im.width < 2 || im.height > kMaxSide || im.width > kMaxSide) return DWT2_E_SHAPE;
+        if (levels < 1 || levels > max_levels(im.height, im.width)) return DWT2_E_LEVELS;
+        total += dwt2::image_ll_bytes(im.height, im.width, levels, es);
+    }
+    *bytes = total;
+    return DWT2_OK;
+}
+
+int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_images, int count,
+                     dwt2_dtype dtype, dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,
+                     unsigned flags, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!host_images || !device_images || !workspace) return DWT2_E_NULL;
+    if (count < 1) return DWT2_E_COUNT;
+    if (wavelet != DWT2_CDF97 && wavelet != DWT2_CDF53_REV) return DWT2_E_WAVELET;
+    if (wavelet != DWT2_CDF97) return DWT2_E_WAVELET;        // batched path: CDF 9/7
+    if (dtype != DWT2_F32 && dtype != DWT2_BF16 && dtype != DWT2_F16) return DWT2_E_DTYPE;
+    if (boundary != DWT2_SYMMETRIC_WHOLE) return DWT2_E_BOUNDARY;
+    if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_KERNEL_MASK)) return DWT2_E_FLAGS;
+    if (((flags & DWT2_FLAG_KERNEL_MASK) >> DWT2_FLAG_KERNEL_SHIFT) > (unsigned)dwt2::kNumConfigs)
+        return DWT2_E_FLAGS;
+    const int cfg = config_of(flags);
+    if (!dwt2::batched_config_supported(cfg)) return DWT2_E_FLAGS;
+    const size_t es = elem_size(dtype);
+    const int core = dwt2::core_rows(dwt2::kConfigs[cfg]);
+    uint64_t tickets = 0;
+    for (int i = 0; i < count; ++i) {
+        const dwt2_image& im = host_images[i];
+        if (!im.src || !im.dst) return DWT2_E_NULL;
+        if (im.height < 2 || im.width < 2 || im.height > kMaxSide || im.width > kMaxSide) return DWT2_E_SHAPE;
+        if (im.src_pitch < im.width || im.dst_pitch < im.width) return DWT2_E_PITCH;
+        if (levels < 1 || levels > max_levels(im.height, im.width)) return DWT2_E_LEVELS;
+        if (ranges_overlap(im.src, span_bytes(im.height, im.width, im.src_pitch, es), im.dst,
+                           span_bytes(im.height, im.width, im.dst_pitch, es)))
+            return DWT2_E_ALIAS;
+        for (int l = 0; l < levels; ++l) tickets += dwt2::level_chunks(im.height, im.width, l, core);
+    }
+    if (tickets >= 0xffffffffull) return DWT2_E_SHAPE;
+    size_t need = 0;
+    const int st = dwt2_workspace_bytes_batched(host_images, count, dtype, levels, &need);
+    if (st) return st;
+    if (workspace_bytes < need) return DWT2_E_WORKSPACE;
+    for (int i = 0; i < count; ++i) {
+        const dwt2_image& im = host_images[i];
+        if (ranges_overlap(workspace, need, im.src, span_bytes(im.height, im.width, im.src_pitch, es)) ||
+            ranges_overlap(workspace, need, im.dst, span_bytes(im.height, im.width, im.dst_pitch, es)))
+            return DWT2_E_ALIAS;
+    }
+    return report(dwt2::launch_fwd_batched(to_dtype(dtype), (flags & DWT2_FLAG_SPLIT) != 0, cfg, device_images,
+                                           count, levels, workspace, (uint32_t)tickets, (hipStream_t)stream));
+}
+
+int dwt2_batched_error(const void* workspace_host_copy) {
+    if (!workspace_host_copy) return DWT2_E_NULL;
+    return (int)static_cast<const dwt2::BatchHeader*>(workspace_host_copy)->error;
 }
 
 const char* dwt2_status_string(int status) {

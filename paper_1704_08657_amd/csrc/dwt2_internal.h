@@ -5,30 +5,45 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dwt2.h"
+
 namespace dwt2 {
 
 enum Direction : int { kForward = 0, kInverse = 1, kAdjoint = 2 };
 enum Wavelet : int { kCdf97 = 0, kCdf53 = 1 };
 enum Dtype : int { kF32 = 0, kBF16 = 1, kF16 = 2, kI32 = 3 };
 
-// Tile geometry shared by host planning and the kernels.  A work-group of
-// `waves` wave64s owns a tile of kTileBX x (waves * rows) blocks of 2x2
-// pixels, of which a halo of kHalo blocks on every side is recomputed and
-// discarded.  Each lane holds two horizontally adjacent blocks for `rows`
-// consecutive block rows.
+// Geometry shared by host planning and the kernels, in blocks of 2x2 pixels.
+// A tile (kAlgoTile) has 128 output columns and waves * rows - 2 * kHalo
+// output rows; a halo of kHalo blocks on every side is recomputed and
+// discarded.  A stream strip (kAlgoStream) has 124 output columns.
 constexpr int kLanes = 64;
 constexpr int kHalo = 2;
-constexpr int kTileBX = 2 * kLanes;                       // 128 blocks
-constexpr int kCoreBX = kTileBX - 2 * kHalo;              // 124 blocks
+constexpr int kTileCoreBX = 2 * kLanes;                   // tile kernel: 128 output columns
+constexpr int kStreamCoreBX = 2 * kLanes - 2 * kHalo;     // stream kernel: 124 (halo in the edge lanes)
 
-struct TileShape {
-    int waves;   // wave64s per work-group, stacked vertically
-    int rows;    // block rows per lane
+// Kernel configurations.
+//  kAlgoTile:   one work-group = `waves` wave64s stacked vertically, one tile
+//               of 128 x (waves * rows) blocks held in VGPRs (`rows` block rows
+//               per lane), one barrier per fused step.
+//  kAlgoStream: every wave64 walks down its own column strip of 128 blocks,
+//               `rows` block rows of loads in flight ahead of the computation;
+//               `waves` strips per work-group; `seg` block rows per segment.
+enum Algo : int { kAlgoTile = 0, kAlgoStream = 1 };
+struct KernelConfig {
+    int algo;
+    int waves;
+    int rows;
+    int seg;
 };
-constexpr TileShape kTileShapes[] = {{8, 8}, {4, 8}, {8, 4}, {16, 4}, {16, 2}, {4, 4}};
-constexpr int kNumTileShapes = 6;
-constexpr int kDefaultTileShape = 0;
-constexpr int core_rows(TileShape s) { return s.waves * s.rows - 2 * kHalo; }
+constexpr KernelConfig kConfigs[] = {
+    {kAlgoTile, 4, 4, 0},    {kAlgoTile, 8, 4, 0},    {kAlgoTile, 6, 4, 0},
+    {kAlgoTile, 4, 6, 0},    {kAlgoTile, 8, 2, 0},    {kAlgoStream, 4, 8, 64},
+    {kAlgoStream, 1, 8, 64}, {kAlgoStream, 4, 8, 32}};
+constexpr int kNumConfigs = 8;
+constexpr int kDefaultConfig = 0;
+// output block rows of one tile (kAlgoTile)
+constexpr int core_rows(KernelConfig c) { return c.waves * c.rows - 2 * kHalo; }
 
 // One level of a transform.  Forward: `in` is the h x w image of this level,
 // `out` the origin of this level's region of the Mallat pyramid (details are
@@ -45,12 +60,22 @@ struct LevelParams {
     int64_t out_ll_pitch;
     int32_t h, w;
     int32_t tiles_x, tiles_y;
-    int32_t vec;     // 1: every row base is aligned for vector access
+    int32_t vec;       // 1: every row base is aligned for vector access
+    int32_t seg_rows;  // kAlgoStream: block rows per segment
 };
 
 // Enqueue one level.  Returns hipSuccess or the launch error.
-// `shape` indexes kTileShapes; tiles_x / tiles_y of `p` must follow it.
-hipError_t launch_level(Direction dir, Wavelet wav, Dtype dt, bool split, int shape,
+// `cfg` indexes kConfigs; tiles_x / tiles_y (and seg_rows) of `p` must
+// follow it: for kAlgoTile the tile grid, for kAlgoStream the number of
+// strip groups (ceil(strips / waves)) and of segments.
+hipError_t launch_level(Direction dir, Wavelet wav, Dtype dt, bool split, int cfg,
                         const LevelParams& p, hipStream_t stream);
+
+// Batched forward CDF 9/7 (planner + persistent kernel) for tile
+// configurations `cfg` with batched_config_supported(cfg).  `tickets` is the
+// total number of work chunks (bounds the persistent grid).
+bool batched_config_supported(int cfg);
+hipError_t launch_fwd_batched(Dtype dt, bool split, int cfg, const dwt2_image* dev_imgs, int count, int levels,
+                              void* ws, uint32_t tickets, hipStream_t s);
 
 }  // namespace dwt2

@@ -1,0 +1,1064 @@
+// Device code shared by the per-direction translation units (dwt2_fwd.hip,
+// dwt2_inv.hip, dwt2_adj.hip); included, not compiled on its own.
+#pragma once
+// Non-separable 2-D lifting DWT kernels for AMD gfx950 (CDNA 4, wave64).
+//
+// Method (Barina et al., "Accelerating Discrete Wavelet Transforms on Parallel
+// Architectures", Section "Proposed Schemes"): every pair of separable lifting
+// steps T_P^V T_P^H and S_U^V S_U^H is fused into one spatial predict T_P and
+// one spatial update S_U over the four polyphase components of 2x2 pixel
+// blocks, so one scale of CDF 9/7 needs 4 barriers (not 8) and the integer
+// CDF 5/3 needs 2 (not 4).  Section "Optimization Approach" (P = P0 + P1,
+// U = U0 + U1, constant parts as barrier-free separable lifting) is the
+// `split` variant.
+//
+// Mapping to gfx950 (not the paper's OpenCL or shader design):
+//   * one work-group = NW wave64s = one tile of 128 x (NW * K) blocks
+//     (e.g. 256 x 128 pixels for NW = K = 8) with a 2-block halo recomputed
+//     on every side;
+//   * each lane owns two horizontally adjacent blocks ("L" and "R") for K
+//     consecutive block rows, all in VGPRs: K rows x 2 blocks x 4 components;
+//   * a step reads neighbours at +1 (predict-shaped: right / down) or at -1
+//     (update-shaped: left / up).  Horizontal neighbours come from the
+//     adjacent lane through DPP wave shifts, vertical ones from the lane's own
+//     registers, except at the boundary between two waves, where the edge row
+//     is published to LDS before the step's single s_barrier (two LDS buffers,
+//     one for each step shape, so one barrier per step suffices);
+//   * loads are 4-pixel vectors per image row, stores are 2-block vectors per
+//     subband row, both coalesced across the wave;
+//   * tiles touching the image border take a path that clamps neighbour
+//     indices into each component's extent (whole-point symmetric extension)
+//     or, for the adjoint, applies the transposed border weights; interior
+//     tiles take a branch-free path;
+//   * the tile index is remapped so that consecutive tiles of the image land
+//     on the same XCD (work-groups are dealt round-robin over the 8 XCDs), so
+//     the halo re-reads of neighbouring tiles hit that XCD's L2.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dwt2_internal.h"
+
+namespace dwt2 {
+namespace kern {
+
+// CDF 9/7 lifting factorisation (Daubechies & Sweldens): predict alpha,
+// update beta, predict gamma, update delta; zeta scales low-pass outputs (and
+// 1/zeta high-pass outputs) per axis so that the low-pass DC gain is sqrt(2):
+// zeta = sqrt(2) / (1 + 2 beta (1 + 2 alpha)).
+constexpr float kAlpha = -1.586134342059924f;
+constexpr float kBeta = -0.052980118572961f;
+constexpr float kGamma = 0.882911075530934f;
+constexpr float kDelta = 0.443506852043971f;
+constexpr double kZeta = 1.1496043988602418;
+constexpr float kZeta2 = (float)(kZeta * kZeta);
+constexpr float kZetaM2 = (float)(1.0 / (kZeta * kZeta));
+
+
+// ---------------------------------------------------------------------------
+// storage types
+// ---------------------------------------------------------------------------
+template <typename T> struct St;
+template <> struct St<float> {
+    using V = float;
+    __device__ static V load(float v) { return v; }
+    __device__ static float store(V v) { return v; }
+};
+template <> struct St<__hip_bfloat16> {
+    using V = float;
+    __device__ static V load(__hip_bfloat16 v) { return __bfloat162float(v); }
+    __device__ static __hip_bfloat16 store(V v) { return __float2bfloat16(v); }
+};
+template <> struct St<__half> {
+    using V = float;
+    __device__ static V load(__half v) { return __half2float(v); }
+    __device__ static __half store(V v) { return __float2half(v); }
+};
+template <> struct St<int32_t> {
+    using V = int;
+    __device__ static V load(int32_t v) { return v; }
+    __device__ static int32_t store(V v) { return v; }
+};
+
+template <typename T> struct alignas(4 * sizeof(T)) Pack4 { T v[4]; };
+template <typename T> struct alignas(2 * sizeof(T)) Pack2 { T v[2]; };
+static_assert(sizeof(Pack4<float>) == 16 && sizeof(Pack2<__half>) == 4, "packed vector layout");
+
+// ---------------------------------------------------------------------------
+// cross-lane shifts (DPP, whole wave64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int dpp_from_right(int v) {   // lane i <- lane i+1
+    return __builtin_amdgcn_update_dpp(0, v, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_from_left(int v) {    // lane i <- lane i-1
+    return __builtin_amdgcn_update_dpp(0, v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float from_right(float v) {
+    return __int_as_float(dpp_from_right(__float_as_int(v)));
+}
+__device__ __forceinline__ float from_left(float v) {
+    return __int_as_float(dpp_from_left(__float_as_int(v)));
+}
+__device__ __forceinline__ int from_right(int v) { return dpp_from_right(v); }
+__device__ __forceinline__ int from_left(int v) { return dpp_from_left(v); }
+
+// ---------------------------------------------------------------------------
+// geometry of one tile as seen by one lane
+// ---------------------------------------------------------------------------
+struct Geo {
+    int gcL;          // global block column of the lane's L block (R = gcL + 1)
+    int gr0;          // global block row of the lane's register row 0
+    int nEr, nOr;     // rows of the even-row (x0, x1) / odd-row (x2, x3) components
+    int nEc, nOc;     // columns of the even-col (x0, x2) / odd-col (x1, x3) components
+};
+
+// Step kinds.
+enum Kind : int {
+    kFloat = 0,      // fused float step (forward, inverse: coefficient sign)
+    kSplitLocal = 1, // not a neighbour step (local constant part)
+    kSplit = 2,      // nonlocal P1 / U1 part of the split
+    kAdj = 3,        // transposed step with transposed border weights
+    kIntFwd = 4,     // reversible 5/3 forward (with neighbour recomputation)
+    kIntInv = 5      // reversible 5/3 inverse
+};
+
+template <typename V> struct Vec4 { V a, b, c, d; };
+
+// ---- predict-shaped block update (reads right / down / down-right) --------
+// Operands: own x0..x3; right: x0R, x2R; down: x0D, x1D; diagonal x0DR.
+template <int KIND, bool EX, bool EY, typename V>
+__device__ __forceinline__ void plus_block(V& x0, V& x1, V& x2, V& x3,
+                                           V x0R, V x2R, V x0D, V x1D, V x0DR,
+                                           int gc, int gr, const Geo& g, float c) {
+    if constexpr (KIND == kAdj) {
+        // transpose of an update-shaped step: odd[k] += c (al_k e[k] + be_k e[k+1])
+        // with al_k = 1 + [k == 0], be_k = [k+1 < ne] + [k+1 == no && ne > no]
+        float alc = 1.f, bec = 1.f, alr = 1.f, ber = 1.f;
+        if constexpr (EX) {
+            alc = (gc == 0) ? 2.f : 1.f;
+            bec = (float)((gc + 1 < g.nEc) + (gc + 1 == g.nOc && g.nEc > g.nOc));
+        }
+        if constexpr (EY) {
+            alr = (gr == 0) ? 2.f : 1.f;
+            ber = (float)((gr + 1 < g.nEr) + (gr + 1 == g.nOr && g.nEr > g.nOr));
+        }
+        const float cc = c * c;
+        const V h0 = fmaf(bec, x0R, alc * x0);
+        const V h0d = fmaf(bec, x0DR, alc * x0D);
+        x3 = fmaf(cc, fmaf(ber, h0d, alr * h0),
+                  fmaf(c, fmaf(ber, x1D, alr * x1), fmaf(c, fmaf(bec, x2R, alc * x2), x3)));
+        x1 = fmaf(c, h0, x1);
+        x2 = fmaf(c, fmaf(ber, x0D, alr * x0), x2);
+    } else {
+        if constexpr (EX || EY) {
+            const bool cR = EX ? (gc + 1 < g.nEc) : true;
+            const bool rD = EY ? (gr + 1 < g.nEr) : true;
+            x0DR = rD ? (cR ? x0DR : x0D) : (cR ? x0R : x0);
+            x0R = cR ? x0R : x0;
+            x2R = cR ? x2R : x2;
+            x0D = rD ? x0D : x0;
+            x1D = rD ? x1D : x1;
+        }
+        if constexpr (KIND == kFloat) {
+            const float cc = c * c;
+            const V t0 = x0 + x0R;
+            const V t1 = x0D + x0DR;
+            x3 = fmaf(cc, t0 + t1, fmaf(c, x1 + x1D, fmaf(c, x2 + x2R, x3)));
+            x1 = fmaf(c, t0, x1);
+            x2 = fmaf(c, x0 + x0D, x2);
+        } else if constexpr (KIND == kSplit) {
+            x3 = fmaf(c * c, x0DR, fmaf(c, x1D, fmaf(c, x2R, x3)));
+            x1 = fmaf(c, x0R, x1);
+            x2 = fmaf(c, x0D, x2);
+        } else if constexpr (KIND == kIntFwd) {
+            // T^H then T^V; x1 one row down after T^H is recomputed.
+            const V x1h = x1 - ((x0 + x0R) >> 1);
+            const V x1hD = x1D - ((x0D + x0DR) >> 1);
+            const V x3h = x3 - ((x2 + x2R) >> 1);
+            x2 = x2 - ((x0 + x0D) >> 1);
+            x3 = x3h - ((x1h + x1hD) >> 1);
+            x1 = x1h;
+        } else if constexpr (KIND == kIntInv) {
+            // undo T^V, then T^H; x2 one column right before T^V is recomputed.
+            const V x2v = x2 + ((x0 + x0D) >> 1);
+            const V x3h = x3 + ((x1 + x1D) >> 1);
+            const V x2Rv = x2R + ((x0R + x0DR) >> 1);
+            x1 = x1 + ((x0 + x0R) >> 1);
+            x3 = x3h + ((x2v + x2Rv) >> 1);
+            x2 = x2v;
+        }
+    }
+}
+
+// ---- update-shaped block update (reads left / up / up-left) ----------------
+// Operands: own x0..x3; left: x1l, x3l; up: x2u, x3u; diagonal x3ul.
+template <int KIND, bool EX, bool EY, typename V>
+__device__ __forceinline__ void minus_block(V& x0, V& x1, V& x2, V& x3,
+                                            V x1l, V x3l, V x2u, V x3u, V x3ul,
+                                            int gc, int gr, const Geo& g, float c) {
+    if constexpr (KIND == kAdj) {
+        // transpose of a predict-shaped step: even[j] += c (a_j o[j] + b_j o[j-1])
+        // with a_j = [j < no] + [j == no-1 && ne == no], b_j = [j >= 1]
+        float ac = 1.f, bc = 1.f, ar = 1.f, br = 1.f;
+        if constexpr (EX) {
+            ac = (float)((gc < g.nOc) + (gc == g.nOc - 1 && g.nEc == g.nOc));
+            bc = (gc >= 1) ? 1.f : 0.f;
+        }
+        if constexpr (EY) {
+            ar = (float)((gr < g.nOr) + (gr == g.nOr - 1 && g.nEr == g.nOr));
+            br = (gr >= 1) ? 1.f : 0.f;
+        }
+        const float cc = c * c;
+        const V h3 = fmaf(bc, x3l, ac * x3);
+        const V h3u = fmaf(bc, x3ul, ac * x3u);
+        x0 = fmaf(cc, fmaf(br, h3u, ar * h3),
+                  fmaf(c, fmaf(br, x2u, ar * x2), fmaf(c, fmaf(bc, x1l, ac * x1), x0)));
+        x1 = fmaf(c, fmaf(br, x3u, ar * x3), x1);
+        x2 = fmaf(c, h3, x2);
+    } else {
+        // Symmetric extension in the polyphase domain: a neighbour index -1
+        // reads index 0 and an index past the end of a component reads its
+        // last sample.  Columns of x1/x3 end at nOc, rows of x2/x3 at nOr.
+        const bool cO = EX ? (gc < g.nOc) : true;
+        const bool cL = EX ? (gc > 0) : true;
+        const bool rO = EY ? (gr < g.nOr) : true;
+        const bool rU = EY ? (gr > 0) : true;
+        const V x1o = cO ? x1 : x1l;          // x1 at (n, m)   clamped
+        const V x1lc = cL ? x1l : x1;         // x1 at (n, m-1) clamped
+        const V x3o = cO ? x3 : x3l;          // x3 at (n, m)   column-clamped
+        const V x3lc = cL ? x3l : x3;         // x3 at (n, m-1)
+        const V x3uo = cO ? x3u : x3ul;       // x3 at (n-1, m)
+        const V x3ulc = cL ? x3ul : x3u;      // x3 at (n-1, m-1)
+        const V X3oo = rO ? x3o : x3uo;       // ... and row-clamped
+        const V X3ol = rO ? x3lc : x3ulc;
+        const V X3uo = rU ? x3uo : x3o;
+        const V X3ul = rU ? x3ulc : x3lc;
+        const V x2o = rO ? x2 : x2u;          // x2 at (n, m)   clamped
+        const V x2uc = rU ? x2u : x2;         // x2 at (n-1, m) clamped
+        if constexpr (KIND == kFloat) {
+            const float cc = c * c;
+            const V s3 = (X3oo + X3ol) + (X3uo + X3ul);
+            x0 = fmaf(cc, s3, fmaf(c, x2uc + x2o, fmaf(c, x1lc + x1o, x0)));
+            x1 = fmaf(c, X3oo + X3uo, x1);
+            x2 = fmaf(c, X3oo + X3ol, x2);
+        } else if constexpr (KIND == kSplit) {
+            x0 = fmaf(c * c, X3ul, fmaf(c, x2uc, fmaf(c, x1lc, x0)));
+            x1 = fmaf(c, X3uo, x1);
+            x2 = fmaf(c, X3ol, x2);
+        } else if constexpr (KIND == kIntFwd) {
+            // S^H then S^V; x2 after S^H in the row above is recomputed.
+            const V x2h_own = x2 + ((x3o + x3lc + 2) >> 2);
+            const V x2h_up = x2u + ((x3uo + x3ulc + 2) >> 2);
+            const V x2ho = rO ? x2h_own : x2h_up;
+            const V x2hu = rU ? x2h_up : x2h_own;
+            x0 = x0 + ((x1lc + x1o + 2) >> 2) + ((x2ho + x2hu + 2) >> 2);
+            x1 = x1 + ((X3oo + X3uo + 2) >> 2);
+            x2 = x2h_own;
+        } else if constexpr (KIND == kIntInv) {
+            // undo S^V, then S^H; x1 before S^V one column left is recomputed.
+            const V x0v = x0 - ((x2o + x2uc + 2) >> 2);
+            const V x1v_own = x1 - ((X3oo + X3uo + 2) >> 2);
+            const V x1v_left = x1l - ((X3ol + X3ul + 2) >> 2);
+            const V x1vo = cO ? x1v_own : x1v_left;
+            const V x1vl = cL ? x1v_left : x1v_own;
+            x0 = x0v - ((x1vl + x1vo + 2) >> 2);
+            x2 = x2 - ((X3oo + X3ol + 2) >> 2);
+            x1 = x1v_own;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile kernel.  A lane holds, for each of its K block rows, four blocks:
+// L and R = tile columns 2*lane and 2*lane+1 (the tile's 128 output
+// columns), and a halo pair E0, E1 that only lanes 0 and 63 use: tile columns
+// -2, -1 (lane 0) and 128, 129 (lane 63).  The output columns of a tile are
+// then aligned to 512-byte subband rows, so every store covers whole cache
+// lines; the halo pair costs extra arithmetic, which is hidden behind memory.
+// a[r][0..3] = L.x0..x3, [4..7] = R, [8..11] = E0, [12..15] = E1.
+// ---------------------------------------------------------------------------
+constexpr int kL = 0, kR = 4, kE0 = 8, kE1 = 12;
+constexpr int kBX = 16;                           // values per register row
+
+struct LaneRole {
+    bool l0, l63;
+};
+
+// Operands of a predict-shaped step for the four blocks of one row, all taken
+// before the step: right neighbour (x0R, x2R), lower (x0D, x1D), lower-right (x0DR).
+template <typename V> struct PlusOps { V x0R[4], x2R[4], x0D[4], x1D[4], x0DR[4]; };
+// Operands of an update-shaped step: left (x1l, x3l), upper (x2u, x3u), upper-left (x3ul).
+template <typename V> struct MinusOps { V x1l[4], x3l[4], x2u[4], x3u[4], x3ul[4]; };
+
+// cur: the row; dn: the row below (x0, x1 used); dnRL0: the right lane's L.x0 of the row below.
+template <typename V>
+__device__ __forceinline__ void gather_plus(const V (&cur)[kBX], const V (&dn)[kBX], V dnRL0, LaneRole lr,
+                                            PlusOps<V>& o) {
+    const V rL0 = from_right(cur[kL + 0]);
+    const V rL2 = from_right(cur[kL + 2]);
+    o.x0R[0] = cur[kR + 0]; o.x2R[0] = cur[kR + 2];                          // L -> R
+    o.x0D[0] = dn[kL + 0]; o.x1D[0] = dn[kL + 1]; o.x0DR[0] = dn[kR + 0];
+    o.x0R[1] = lr.l63 ? cur[kE0 + 0] : rL0;                                  // R -> next lane's L
+    o.x2R[1] = lr.l63 ? cur[kE0 + 2] : rL2;                                  //      (E0 in lane 63)
+    o.x0D[1] = dn[kR + 0]; o.x1D[1] = dn[kR + 1]; o.x0DR[1] = lr.l63 ? dn[kE0 + 0] : dnRL0;
+    o.x0R[2] = cur[kE1 + 0]; o.x2R[2] = cur[kE1 + 2];                        // E0 -> E1
+    o.x0D[2] = dn[kE0 + 0]; o.x1D[2] = dn[kE0 + 1]; o.x0DR[2] = dn[kE1 + 0];
+    o.x0R[3] = lr.l0 ? cur[kL + 0] : cur[kE1 + 0];                           // E1 -> L in lane 0
+    o.x2R[3] = lr.l0 ? cur[kL + 2] : cur[kE1 + 2];                           //   (outermost halo otherwise)
+    o.x0D[3] = dn[kE1 + 0]; o.x1D[3] = dn[kE1 + 1]; o.x0DR[3] = lr.l0 ? dn[kL + 0] : dn[kE1 + 0];
+}
+
+// cur: the row; up: the row above (x2, x3 used); upLR3: the left lane's R.x3 of the row above.
+template <typename V>
+__device__ __forceinline__ void gather_minus(const V (&cur)[kBX], const V (&up)[kBX], V upLR3, LaneRole lr,
+                                             MinusOps<V>& o) {
+    const V lR1 = from_left(cur[kR + 1]);
+    const V lR3 = from_left(cur[kR + 3]);
+    o.x1l[0] = lr.l0 ? cur[kE1 + 1] : lR1;                                   // L <- previous lane's R
+    o.x3l[0] = lr.l0 ? cur[kE1 + 3] : lR3;                                   //      (E1 in lane 0)
+    o.x2u[0] = up[kL + 2]; o.x3u[0] = up[kL + 3]; o.x3ul[0] = lr.l0 ? up[kE1 + 3] : upLR3;
+    o.x1l[1] = cur[kL + 1]; o.x3l[1] = cur[kL + 3];                          // R <- L
+    o.x2u[1] = up[kR + 2]; o.x3u[1] = up[kR + 3]; o.x3ul[1] = up[kL + 3];
+    o.x1l[2] = lr.l63 ? cur[kR + 1] : cur[kE0 + 1];                          // E0 <- R in lane 63
+    o.x3l[2] = lr.l63 ? cur[kR + 3] : cur[kE0 + 3];                          //   (outermost halo otherwise)
+    o.x2u[2] = up[kE0 + 2]; o.x3u[2] = up[kE0 + 3]; o.x3ul[2] = lr.l63 ? up[kR + 3] : up[kE0 + 3];
+    o.x1l[3] = cur[kE0 + 1]; o.x3l[3] = cur[kE0 + 3];                        // E1 <- E0
+    o.x2u[3] = up[kE1 + 2]; o.x3u[3] = up[kE1 + 3]; o.x3ul[3] = up[kE0 + 3];
+}
+
+template <int KIND, bool EX, bool EY, typename V>
+__device__ __forceinline__ void apply_plus(V (&cur)[kBX], const PlusOps<V>& o, const int (&gc)[4], int gr,
+                                           const Geo& g, float c) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        plus_block<KIND, EX, EY>(cur[4 * b], cur[4 * b + 1], cur[4 * b + 2], cur[4 * b + 3], o.x0R[b], o.x2R[b],
+                                 o.x0D[b], o.x1D[b], o.x0DR[b], gc[b], gr, g, c);
+}
+
+template <int KIND, bool EX, bool EY, typename V>
+__device__ __forceinline__ void apply_minus(V (&cur)[kBX], const MinusOps<V>& o, const int (&gc)[4], int gr,
+                                            const Geo& g, float c) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        minus_block<KIND, EX, EY>(cur[4 * b], cur[4 * b + 1], cur[4 * b + 2], cur[4 * b + 3], o.x1l[b], o.x3l[b],
+                                  o.x2u[b], o.x3u[b], o.x3ul[b], gc[b], gr, g, c);
+}
+
+// Edge rows exchanged between the waves of a tile: x0, x1 of the top row (read
+// by predict-shaped steps of the wave above) and x2, x3 of the bottom row (read
+// by update-shaped steps of the wave below), for the four blocks of a lane.
+template <typename V> struct Edge8 { Vec4<V> m, e; };
+
+template <int K, typename V>
+__device__ __forceinline__ void publish_top(V (&a)[K][kBX], Edge8<V> (*buf)[kLanes], int lane, int wv) {
+    buf[wv][lane].m = Vec4<V>{a[0][kL + 0], a[0][kL + 1], a[0][kR + 0], a[0][kR + 1]};
+    buf[wv][lane].e = Vec4<V>{a[0][kE0 + 0], a[0][kE0 + 1], a[0][kE1 + 0], a[0][kE1 + 1]};
+}
+template <int K, typename V>
+__device__ __forceinline__ void publish_bottom(V (&a)[K][kBX], Edge8<V> (*buf)[kLanes], int lane, int wv) {
+    buf[wv][lane].m = Vec4<V>{a[K - 1][kL + 2], a[K - 1][kL + 3], a[K - 1][kR + 2], a[K - 1][kR + 3]};
+    buf[wv][lane].e = Vec4<V>{a[K - 1][kE0 + 2], a[K - 1][kE0 + 3], a[K - 1][kE1 + 2], a[K - 1][kE1 + 3]};
+}
+
+// Predict-shaped step over the tile: rows top to bottom, so row r+1 is still
+// unmodified when row r reads it.
+template <int KIND, bool EDGE, int NW, int K, typename V>
+__device__ __forceinline__ void plus_step(V (&a)[K][kBX], Edge8<V> (*buf)[kLanes], int lane, int wv,
+                                          const Geo& g, const int (&gc)[4], LaneRole lr, float c) {
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        PlusOps<V> o;
+        if (r + 1 < K) {
+            gather_plus(a[r], a[r + 1], from_right(a[r + 1][kL + 0]), lr, o);
+        } else {
+            V dn[kBX];
+            V rl0;
+            if (wv + 1 < NW) {
+                const Edge8<V> q = buf[wv + 1][lane];
+                dn[kL + 0] = q.m.a; dn[kL + 1] = q.m.b; dn[kR + 0] = q.m.c; dn[kR + 1] = q.m.d;
+                dn[kE0 + 0] = q.e.a; dn[kE0 + 1] = q.e.b; dn[kE1 + 0] = q.e.c; dn[kE1 + 1] = q.e.d;
+                rl0 = buf[wv + 1][lane < kLanes - 1 ? lane + 1 : lane].m.a;
+            } else {                              // below the tile: halo, any finite value
+#pragma unroll
+                for (int q = 0; q < kBX; ++q) dn[q] = a[r][q];
+                rl0 = from_right(a[r][kL + 0]);
+            }
+            gather_plus(a[r], dn, rl0, lr, o);
+        }
+        apply_plus<KIND, EDGE, EDGE>(a[r], o, gc, g.gr0 + r, g, c);
+    }
+}
+
+// Update-shaped step over the tile: rows bottom to top.
+template <int KIND, bool EDGE, int NW, int K, typename V>
+__device__ __forceinline__ void minus_step(V (&a)[K][kBX], Edge8<V> (*buf)[kLanes], int lane, int wv,
+                                           const Geo& g, const int (&gc)[4], LaneRole lr, float c) {
+#pragma unroll
+    for (int r = K - 1; r >= 0; --r) {
+        MinusOps<V> o;
+        if (r > 0) {
+            gather_minus(a[r], a[r - 1], from_left(a[r - 1][kR + 3]), lr, o);
+        } else {
+            V up[kBX];
+            V lr3;
+            if (wv > 0) {
+                const Edge8<V> q = buf[wv - 1][lane];
+                up[kL + 2] = q.m.a; up[kL + 3] = q.m.b; up[kR + 2] = q.m.c; up[kR + 3] = q.m.d;
+                up[kE0 + 2] = q.e.a; up[kE0 + 3] = q.e.b; up[kE1 + 2] = q.e.c; up[kE1 + 3] = q.e.d;
+                lr3 = buf[wv - 1][lane > 0 ? lane - 1 : 0].m.d;
+            } else {                              // above the tile: halo
+#pragma unroll
+                for (int q = 0; q < kBX; ++q) up[q] = a[r][q];
+                lr3 = from_left(a[r][kR + 3]);
+            }
+            gather_minus(a[r], up, lr3, lr, o);
+        }
+        apply_minus<KIND, EDGE, EDGE>(a[r], o, gc, g.gr0 + r, g, c);
+    }
+}
+
+// Constant parts of the split (no neighbour access): separable lifting with
+// P0 = c (horizontal, then vertical) and with U0 = c, for every block.
+template <int K, typename V>
+__device__ __forceinline__ void local_predict(V (&a)[K][kBX], float c) {
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+#pragma unroll
+        for (int b = 0; b < kBX; b += 4) {
+            a[r][b + 1] = fmaf(c, a[r][b + 0], a[r][b + 1]);
+            a[r][b + 3] = fmaf(c, a[r][b + 2], a[r][b + 3]);
+            a[r][b + 2] = fmaf(c, a[r][b + 0], a[r][b + 2]);
+            a[r][b + 3] = fmaf(c, a[r][b + 1], a[r][b + 3]);
+        }
+}
+template <int K, typename V>
+__device__ __forceinline__ void local_update(V (&a)[K][kBX], float c) {
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+#pragma unroll
+        for (int b = 0; b < kBX; b += 4) {
+            a[r][b + 0] = fmaf(c, a[r][b + 1], a[r][b + 0]);
+            a[r][b + 2] = fmaf(c, a[r][b + 3], a[r][b + 2]);
+            a[r][b + 0] = fmaf(c, a[r][b + 2], a[r][b + 0]);
+            a[r][b + 1] = fmaf(c, a[r][b + 3], a[r][b + 1]);
+        }
+}
+template <int K, typename V>
+__device__ __forceinline__ void scale(V (&a)[K][kBX], float s0, float s3) {
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+#pragma unroll
+        for (int b = 0; b < kBX; b += 4) {
+            a[r][b + 0] *= s0;
+            a[r][b + 3] *= s3;
+        }
+}
+
+// The step program of one scale.  Each "sync" is the single barrier of one
+// fused step; the LDS edge row it guards is published just before it.
+template <int DIR, int WAV, bool EDGE, bool SPLIT, int NW, int K, typename V>
+__device__ __forceinline__ void run(V (&a)[K][kBX], Edge8<V> (*bT)[kLanes], Edge8<V> (*bS)[kLanes],
+                                    int lane, int wv, const Geo& g, const int (&gc)[4], LaneRole lr) {
+#define DWT2_PLUS(KIND_, c_) publish_top(a, bT, lane, wv); __syncthreads(); \
+    plus_step<KIND_, EDGE, NW>(a, bT, lane, wv, g, gc, lr, (c_));
+#define DWT2_MINUS(KIND_, c_) publish_bottom(a, bS, lane, wv); __syncthreads(); \
+    minus_step<KIND_, EDGE, NW>(a, bS, lane, wv, g, gc, lr, (c_));
+    if constexpr (WAV == kCdf53) {
+        if constexpr (DIR == kForward) {
+            DWT2_PLUS(kIntFwd, 0.f)
+            DWT2_MINUS(kIntFwd, 0.f)
+        } else {
+            DWT2_MINUS(kIntInv, 0.f)
+            DWT2_PLUS(kIntInv, 0.f)
+        }
+    } else if constexpr (DIR == kForward) {
+        if constexpr (SPLIT) {
+            local_predict(a, kAlpha);
+            DWT2_PLUS(kSplit, kAlpha) local_update(a, kBeta);
+            DWT2_MINUS(kSplit, kBeta) local_predict(a, kGamma);
+            DWT2_PLUS(kSplit, kGamma) local_update(a, kDelta);
+            DWT2_MINUS(kSplit, kDelta)
+        } else {
+            DWT2_PLUS(kFloat, kAlpha)
+            DWT2_MINUS(kFloat, kBeta)
+            DWT2_PLUS(kFloat, kGamma)
+            DWT2_MINUS(kFloat, kDelta)
+        }
+        scale(a, kZeta2, kZetaM2);
+    } else if constexpr (DIR == kInverse) {
+        scale(a, kZetaM2, kZeta2);
+        if constexpr (SPLIT) {
+            DWT2_MINUS(kSplit, -kDelta) local_update(a, -kDelta);
+            DWT2_PLUS(kSplit, -kGamma) local_predict(a, -kGamma);
+            DWT2_MINUS(kSplit, -kBeta) local_update(a, -kBeta);
+            DWT2_PLUS(kSplit, -kAlpha) local_predict(a, -kAlpha);
+        } else {
+            DWT2_MINUS(kFloat, -kDelta)
+            DWT2_PLUS(kFloat, -kGamma)
+            DWT2_MINUS(kFloat, -kBeta)
+            DWT2_PLUS(kFloat, -kAlpha)
+        }
+    } else {
+        // W^T = T_1^T S_1^T T_2^T S_2^T Z: transposed steps in reverse order;
+        // the transpose of an update is predict-shaped and vice versa.
+        scale(a, kZeta2, kZetaM2);
+        DWT2_PLUS(kAdj, kDelta)
+        DWT2_MINUS(kAdj, kGamma)
+        DWT2_PLUS(kAdj, kBeta)
+        DWT2_MINUS(kAdj, kAlpha)
+    }
+#undef DWT2_PLUS
+#undef DWT2_MINUS
+}
+
+// ---------------------------------------------------------------------------
+// global memory access
+// ---------------------------------------------------------------------------
+// Vector stores of whole output rows are streamed (nontemporal): the
+// outputs are not read again by this launch, and the stores of a tile cover
+// whole cache lines.
+template <typename T>
+__device__ __forceinline__ void nt_store2(T* p, T a, T b) {
+    if constexpr (sizeof(T) == 4) {
+        typedef int v2 __attribute__((ext_vector_type(2)));
+        v2 q;
+        q.x = __builtin_bit_cast(int, a);
+        q.y = __builtin_bit_cast(int, b);
+        __builtin_nontemporal_store(q, reinterpret_cast<v2*>(p));
+    } else {
+        typedef short v2 __attribute__((ext_vector_type(2)));
+        v2 q;
+        q.x = __builtin_bit_cast(short, a);
+        q.y = __builtin_bit_cast(short, b);
+        __builtin_nontemporal_store(q, reinterpret_cast<v2*>(p));
+    }
+}
+template <typename T>
+__device__ __forceinline__ void nt_store4(T* p, T a, T b, T c, T d) {
+    if constexpr (sizeof(T) == 4) {
+        typedef int v4 __attribute__((ext_vector_type(4)));
+        v4 q;
+        q.x = __builtin_bit_cast(int, a); q.y = __builtin_bit_cast(int, b);
+        q.z = __builtin_bit_cast(int, c); q.w = __builtin_bit_cast(int, d);
+        __builtin_nontemporal_store(q, reinterpret_cast<v4*>(p));
+    } else {
+        typedef short v4 __attribute__((ext_vector_type(4)));
+        v4 q;
+        q.x = __builtin_bit_cast(short, a); q.y = __builtin_bit_cast(short, b);
+        q.z = __builtin_bit_cast(short, c); q.w = __builtin_bit_cast(short, d);
+        __builtin_nontemporal_store(q, reinterpret_cast<v4*>(p));
+    }
+}
+
+// Four consecutive samples of one image row starting at column c (a multiple
+// of 4); samples outside [0, w) or rows outside [0, h) read as 0.
+template <typename T, bool EDGE>
+__device__ __forceinline__ void load4(const T* base, int64_t pitch, int row, int c, int h, int w,
+                                      bool vec, typename St<T>::V& v0, typename St<T>::V& v1,
+                                      typename St<T>::V& v2, typename St<T>::V& v3) {
+    using V = typename St<T>::V;
+    v0 = v1 = v2 = v3 = V(0);
+    if (EDGE && (row < 0 || row >= h || c < 0 || c >= w)) return;
+    const T* p = base + (int64_t)row * pitch + c;
+    if (vec && (!EDGE || c + 3 < w)) {
+        const Pack4<T> q = *reinterpret_cast<const Pack4<T>*>(p);
+        v0 = St<T>::load(q.v[0]); v1 = St<T>::load(q.v[1]);
+        v2 = St<T>::load(q.v[2]); v3 = St<T>::load(q.v[3]);
+    } else {
+        v0 = St<T>::load(p[0]);
+        if (!EDGE || c + 1 < w) v1 = St<T>::load(p[1]);
+        if (!EDGE || c + 2 < w) v2 = St<T>::load(p[2]);
+        if (!EDGE || c + 3 < w) v3 = St<T>::load(p[3]);
+    }
+}
+
+template <typename T, bool EDGE>
+__device__ __forceinline__ void store4(T* base, int64_t pitch, int row, int c, int h, int w, bool vec,
+                                       typename St<T>::V v0, typename St<T>::V v1,
+                                       typename St<T>::V v2, typename St<T>::V v3) {
+    if (EDGE && (row >= h || c >= w)) return;
+    T* p = base + (int64_t)row * pitch + c;
+    if (vec && (!EDGE || c + 3 < w)) {
+        nt_store4(p, St<T>::store(v0), St<T>::store(v1), St<T>::store(v2), St<T>::store(v3));
+    } else {
+        p[0] = St<T>::store(v0);
+        if (!EDGE || c + 1 < w) p[1] = St<T>::store(v1);
+        if (!EDGE || c + 2 < w) p[2] = St<T>::store(v2);
+        if (!EDGE || c + 3 < w) p[3] = St<T>::store(v3);
+    }
+}
+
+// Two consecutive samples (blocks gc, gc+1; gc even) of one subband row with
+// `ncols` columns.
+template <typename T, bool EDGE>
+__device__ __forceinline__ void load2(const T* rowp, int gc, int ncols, bool row_ok, bool vec,
+                                      typename St<T>::V& v0, typename St<T>::V& v1) {
+    using V = typename St<T>::V;
+    v0 = v1 = V(0);
+    if (EDGE && (!row_ok || gc < 0 || gc >= ncols)) return;
+    const T* p = rowp + gc;
+    if (vec && (!EDGE || gc + 1 < ncols)) {
+        const Pack2<T> q = *reinterpret_cast<const Pack2<T>*>(p);
+        v0 = St<T>::load(q.v[0]); v1 = St<T>::load(q.v[1]);
+    } else {
+        v0 = St<T>::load(p[0]);
+        if (!EDGE || gc + 1 < ncols) v1 = St<T>::load(p[1]);
+    }
+}
+
+template <typename T, bool EDGE>
+__device__ __forceinline__ void store2(T* rowp, int gc, int ncols, bool vec,
+                                       typename St<T>::V v0, typename St<T>::V v1) {
+    if (EDGE && gc >= ncols) return;
+    T* p = rowp + gc;
+    if (vec && (!EDGE || gc + 1 < ncols)) {
+        nt_store2(p, St<T>::store(v0), St<T>::store(v1));
+    } else {
+        p[0] = St<T>::store(v0);
+        if (!EDGE || gc + 1 < ncols) p[1] = St<T>::store(v1);
+    }
+}
+
+// Load the tile (halo included) into registers.
+template <int DIR, typename T, bool EDGE, int K>
+__device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][kBX], const LevelParams& P, const Geo& g,
+                                          int gcE0, LaneRole lr) {
+    using V = typename St<T>::V;
+    const bool vec = P.vec != 0;
+    const bool halo_lane = lr.l0 || lr.l63;
+    if constexpr (DIR == kForward) {
+        const T* in = static_cast<const T*>(P.in);
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const int row = 2 * (g.gr0 + r);
+            load4<T, EDGE>(in, P.in_pitch, row, 2 * g.gcL, P.h, P.w, vec, a[r][kL + 0], a[r][kL + 1], a[r][kR + 0],
+                           a[r][kR + 1]);
+            load4<T, EDGE>(in, P.in_pitch, row + 1, 2 * g.gcL, P.h, P.w, vec, a[r][kL + 2], a[r][kL + 3],
+                           a[r][kR + 2], a[r][kR + 3]);
+            a[r][kE0 + 0] = a[r][kE0 + 1] = a[r][kE1 + 0] = a[r][kE1 + 1] = V(0);
+            a[r][kE0 + 2] = a[r][kE0 + 3] = a[r][kE1 + 2] = a[r][kE1 + 3] = V(0);
+            if (halo_lane) {
+                load4<T, EDGE>(in, P.in_pitch, row, 2 * gcE0, P.h, P.w, vec, a[r][kE0 + 0], a[r][kE0 + 1],
+                               a[r][kE1 + 0], a[r][kE1 + 1]);
+                load4<T, EDGE>(in, P.in_pitch, row + 1, 2 * gcE0, P.h, P.w, vec, a[r][kE0 + 2], a[r][kE0 + 3],
+                               a[r][kE1 + 2], a[r][kE1 + 3]);
+            }
+        }
+    } else {
+        const T* ll = static_cast<const T*>(P.in_ll);
+        const T* det = static_cast<const T*>(P.in);
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const int gr = g.gr0 + r;
+            const bool rE = gr >= 0 && gr < g.nEr;
+            const bool rO = gr >= 0 && gr < g.nOr;
+            const int64_t gre = rE ? gr : 0, gro = rO ? gr : 0;
+            const T* p0 = ll + gre * P.in_ll_pitch;
+            const T* p1 = det + gre * P.in_pitch + g.nEc;
+            const T* p2 = det + (g.nEr + gro) * P.in_pitch;
+            const T* p3 = det + (g.nEr + gro) * P.in_pitch + g.nEc;
+            load2<T, EDGE>(p0, g.gcL, g.nEc, rE, vec, a[r][kL + 0], a[r][kR + 0]);
+            load2<T, EDGE>(p1, g.gcL, g.nOc, rE, vec, a[r][kL + 1], a[r][kR + 1]);
+            load2<T, EDGE>(p2, g.gcL, g.nEc, rO, vec, a[r][kL + 2], a[r][kR + 2]);
+            load2<T, EDGE>(p3, g.gcL, g.nOc, rO, vec, a[r][kL + 3], a[r][kR + 3]);
+#pragma unroll
+            for (int q = kE0; q < kBX; ++q) a[r][q] = V(0);
+            if (halo_lane) {
+                load2<T, EDGE>(p0, gcE0, g.nEc, rE, vec, a[r][kE0 + 0], a[r][kE1 + 0]);
+                load2<T, EDGE>(p1, gcE0, g.nOc, rE, vec, a[r][kE0 + 1], a[r][kE1 + 1]);
+                load2<T, EDGE>(p2, gcE0, g.nEc, rO, vec, a[r][kE0 + 2], a[r][kE1 + 2]);
+                load2<T, EDGE>(p3, gcE0, g.nOc, rO, vec, a[r][kE0 + 3], a[r][kE1 + 3]);
+            }
+        }
+    }
+}
+
+// Store the core of the tile: the L and R blocks of every lane, halo rows dropped.
+template <int DIR, typename T, bool EDGE, int NW, int K>
+__device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][kBX], const LevelParams& P,
+                                           const Geo& g, int wv) {
+    constexpr int kCoreBY = NW * K - 2 * kHalo;
+    const bool vec = P.vec != 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const int tr = wv * K + r;                // row within the tile
+        if (tr < kHalo || tr >= kHalo + kCoreBY) continue;
+        const int gr = g.gr0 + r;
+        if (EDGE && gr >= g.nEr) continue;
+        if constexpr (DIR == kForward) {
+            T* ll = static_cast<T*>(P.out_ll);
+            T* det = static_cast<T*>(P.out);
+            store2<T, EDGE>(ll + (int64_t)gr * P.out_ll_pitch, g.gcL, g.nEc, vec, a[r][kL + 0], a[r][kR + 0]);
+            store2<T, EDGE>(det + (int64_t)gr * P.out_pitch + g.nEc, g.gcL, g.nOc, vec, a[r][kL + 1], a[r][kR + 1]);
+            if (!EDGE || gr < g.nOr) {
+                store2<T, EDGE>(det + (int64_t)(g.nEr + gr) * P.out_pitch, g.gcL, g.nEc, vec, a[r][kL + 2],
+                                a[r][kR + 2]);
+                store2<T, EDGE>(det + (int64_t)(g.nEr + gr) * P.out_pitch + g.nEc, g.gcL, g.nOc, vec,
+                                a[r][kL + 3], a[r][kR + 3]);
+            }
+        } else {
+            T* img = static_cast<T*>(P.out);
+            const int c = 2 * g.gcL;
+            store4<T, EDGE>(img, P.out_pitch, 2 * gr, c, P.h, P.w, vec, a[r][kL + 0], a[r][kL + 1], a[r][kR + 0],
+                            a[r][kR + 1]);
+            store4<T, EDGE>(img, P.out_pitch, 2 * gr + 1, c, P.h, P.w, vec, a[r][kL + 2], a[r][kL + 3],
+                            a[r][kR + 2], a[r][kR + 3]);
+        }
+    }
+}
+
+// One tile (tx, ty) of one level: load, the fused steps, store.  The LDS
+// edge buffers belong to the calling work-group.
+template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K>
+__device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty, Edge8<typename St<T>::V> (*bufT)[kLanes],
+                                          Edge8<typename St<T>::V> (*bufS)[kLanes], int lane, int wv) {
+    using V = typename St<T>::V;
+    constexpr int kCoreBY = NW * K - 2 * kHalo;
+    Geo g;
+    g.nEr = (P.h + 1) >> 1; g.nOr = P.h >> 1;
+    g.nEc = (P.w + 1) >> 1; g.nOc = P.w >> 1;
+    const int cb0 = tx * kTileCoreBX, rb0 = ty * kCoreBY;
+    LaneRole lr;
+    lr.l0 = lane == 0;
+    lr.l63 = lane == kLanes - 1;
+    g.gcL = cb0 + 2 * lane;
+    g.gr0 = rb0 - kHalo + wv * K;
+    const int gcE0 = lr.l0 ? cb0 - kHalo : cb0 + kTileCoreBX;
+    const int gc[4] = {g.gcL, g.gcL + 1, gcE0, gcE0 + 1};
+    // Interior tile: every loaded block has all four components and no
+    // neighbour index of the core's dependency cone needs clamping.
+    const bool interior = rb0 - kHalo >= 0 && cb0 - kHalo >= 0 &&
+                          rb0 + kCoreBY + kHalo <= g.nOr && cb0 + kTileCoreBX + kHalo <= g.nOc;
+    V a[K][kBX];
+    if (interior) {
+        load_tile<DIR, T, false>(a, P, g, gcE0, lr);
+        run<DIR, WAV, false, SPLIT, NW>(a, bufT, bufS, lane, wv, g, gc, lr);
+        store_tile<DIR, T, false, NW>(a, P, g, wv);
+    } else {
+        load_tile<DIR, T, true>(a, P, g, gcE0, lr);
+        run<DIR, WAV, true, false, NW>(a, bufT, bufS, lane, wv, g, gc, lr);
+        store_tile<DIR, T, true, NW>(a, P, g, wv);
+    }
+}
+
+template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K>
+__global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
+    using V = typename St<T>::V;
+    __shared__ Edge8<V> bufT[NW][kLanes];
+    __shared__ Edge8<V> bufS[NW][kLanes];
+    const int lane = threadIdx.x & (kLanes - 1);
+    // the wave index is uniform: keep it (and every row address) in SGPRs
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+    // Work-groups are dealt round-robin over the 8 XCDs; give each XCD a
+    // contiguous run of tiles (row-major) so neighbouring halos share its L2.
+    const int nt = P.tiles_x * P.tiles_y;
+    const int per = (nt + 7) >> 3;
+    const int t = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if (t >= nt) return;                          // uniform over the work-group
+    const int ty = t / P.tiles_x;
+    const int tx = t - ty * P.tiles_x;
+    tile_body<DIR, WAV, T, SPLIT, NW, K>(P, tx, ty, bufT, bufS, lane, wv);
+}
+
+// ===========================================================================
+// Streaming kernel: one wave64 marches down a column strip of the image.
+//
+// The strip is 128 blocks wide (2 per lane, a 2-block halo on each side, as
+// in the tile kernel); the wave walks a segment of block rows top to bottom.
+// Each iteration brings one new block row into a small register window and
+// advances every fused step by one row: a predict-shaped step on row r needs
+// row r+1 at the previous stage, so it runs one row behind that stage; an
+// update-shaped step on row r needs row r-1, which is already done, so it
+// runs in the same row as the previous stage.  For CDF 9/7 forward the steps
+// T, S, T, S run on rows i-1, i-1, i-2, i-2 when row i arrives; the row
+// leaving the window is final and stored.  The value an update-shaped step
+// reads from the row above must be taken before that row was itself updated:
+// it is saved just before the update.  Horizontal neighbours come from the
+// adjacent lane (DPP); there is no LDS and no barrier, and loads run a few
+// rows ahead of the computation.  A segment re-reads only the 2 block rows
+// above and below it.
+// ===========================================================================
+struct StepSpec {
+    bool plus;    // predict-shaped (reads the row below) or update-shaped
+    int kind;     // Kind of the fused step
+    float c;      // its coefficient
+    int after;    // split: constant part applied to the same row right after
+                  // (0 none, 1 predict-local, 2 update-local)
+    float ca;     // coefficient of that constant part
+};
+
+template <int DIR, int WAV, bool SPLIT> struct Prog;
+
+template <bool SPLIT> struct Prog<kForward, kCdf97, SPLIT> {
+    static constexpr int N = 4;
+    static constexpr StepSpec kSteps[N] = {
+        {true, SPLIT ? kSplit : kFloat, kAlpha, SPLIT ? 2 : 0, kBeta},
+        {false, SPLIT ? kSplit : kFloat, kBeta, SPLIT ? 1 : 0, kGamma},
+        {true, SPLIT ? kSplit : kFloat, kGamma, SPLIT ? 2 : 0, kDelta},
+        {false, SPLIT ? kSplit : kFloat, kDelta, 0, 0.f}};
+    static constexpr int kPreLocal = SPLIT ? 1 : 0;     // constant part of the first predict
+    static constexpr float kPreLocalC = kAlpha;
+    static constexpr bool kPreScale = false;
+    static constexpr float kPre0 = 1.f, kPre3 = 1.f;
+    static constexpr bool kPostScale = true;
+    static constexpr float kPost0 = kZeta2, kPost3 = kZetaM2;
+};
+template <bool SPLIT> struct Prog<kInverse, kCdf97, SPLIT> {
+    static constexpr int N = 4;
+    static constexpr StepSpec kSteps[N] = {
+        {false, SPLIT ? kSplit : kFloat, -kDelta, SPLIT ? 2 : 0, -kDelta},
+        {true, SPLIT ? kSplit : kFloat, -kGamma, SPLIT ? 1 : 0, -kGamma},
+        {false, SPLIT ? kSplit : kFloat, -kBeta, SPLIT ? 2 : 0, -kBeta},
+        {true, SPLIT ? kSplit : kFloat, -kAlpha, SPLIT ? 1 : 0, -kAlpha}};
+    static constexpr int kPreLocal = 0;
+    static constexpr float kPreLocalC = 0.f;
+    static constexpr bool kPreScale = true;
+    static constexpr float kPre0 = kZetaM2, kPre3 = kZeta2;
+    static constexpr bool kPostScale = false;
+    static constexpr float kPost0 = 1.f, kPost3 = 1.f;
+};
+template <bool SPLIT> struct Prog<kAdjoint, kCdf97, SPLIT> {
+    static constexpr int N = 4;
+    static constexpr StepSpec kSteps[N] = {
+        {true, kAdj, kDelta, 0, 0.f}, {false, kAdj, kGamma, 0, 0.f},
+        {true, kAdj, kBeta, 0, 0.f}, {false, kAdj, kAlpha, 0, 0.f}};
+    static constexpr int kPreLocal = 0;
+    static constexpr float kPreLocalC = 0.f;
+    static constexpr bool kPreScale = true;
+    static constexpr float kPre0 = kZeta2, kPre3 = kZetaM2;
+    static constexpr bool kPostScale = false;
+    static constexpr float kPost0 = 1.f, kPost3 = 1.f;
+};
+template <bool SPLIT> struct Prog<kForward, kCdf53, SPLIT> {
+    static constexpr int N = 2;
+    static constexpr StepSpec kSteps[N] = {{true, kIntFwd, 0.f, 0, 0.f}, {false, kIntFwd, 0.f, 0, 0.f}};
+    static constexpr int kPreLocal = 0;
+    static constexpr float kPreLocalC = 0.f;
+    static constexpr bool kPreScale = false;
+    static constexpr float kPre0 = 1.f, kPre3 = 1.f;
+    static constexpr bool kPostScale = false;
+    static constexpr float kPost0 = 1.f, kPost3 = 1.f;
+};
+template <bool SPLIT> struct Prog<kInverse, kCdf53, SPLIT> {
+    static constexpr int N = 2;
+    static constexpr StepSpec kSteps[N] = {{false, kIntInv, 0.f, 0, 0.f}, {true, kIntInv, 0.f, 0, 0.f}};
+    static constexpr int kPreLocal = 0;
+    static constexpr float kPreLocalC = 0.f;
+    static constexpr bool kPreScale = false;
+    static constexpr float kPre0 = 1.f, kPre3 = 1.f;
+    static constexpr bool kPostScale = false;
+    static constexpr float kPost0 = 1.f, kPost3 = 1.f;
+};
+
+// Rows behind the newest row at which step k runs.
+template <class PR>
+constexpr int step_lag(int k) {
+    int lag = 0;
+    for (int j = 0; j <= k; ++j) lag += PR::kSteps[j].plus ? 1 : 0;
+    return lag;
+}
+template <class PR>
+constexpr int max_lag() { return step_lag<PR>(PR::N - 1); }
+
+// Predict-shaped step on one row (cur) reading the row below (dn).
+template <int KIND, bool EX, bool EY, typename V>
+__device__ __forceinline__ void plus_row(V (&cur)[8], const V (&dn)[8], int gcL, int gr, const Geo& g, float c) {
+    const V rrow = from_right(cur[0]);
+    const V rR2 = from_right(cur[2]);
+    const V dRR = from_right(dn[0]);
+    plus_block<KIND, EX, EY>(cur[0], cur[1], cur[2], cur[3], cur[4], cur[6], dn[0], dn[1], dn[4], gcL, gr, g, c);
+    plus_block<KIND, EX, EY>(cur[4], cur[5], cur[6], cur[7], rrow, rR2, dn[4], dn[5], dRR, gcL + 1, gr, g, c);
+}
+
+// Update-shaped step on one row reading x2 and x3 of the row above (up2, up3:
+// L then R), both taken just before that row's own update: later steps of
+// the pipeline (the constant predict part of the split) may change them.
+template <int KIND, bool EX, bool EY, typename V>
+__device__ __forceinline__ void minus_row(V (&cur)[8], const V (&up)[4], int gcL, int gr,
+                                          const Geo& g, float c) {
+    const V lL1 = from_left(cur[5]);
+    const V lL3 = from_left(cur[7]);
+    const V uLL3 = from_left(up[3]);
+    minus_block<KIND, EX, EY>(cur[4], cur[5], cur[6], cur[7], cur[1], cur[3], up[1], up[3], up[2],
+                              gcL + 1, gr, g, c);
+    minus_block<KIND, EX, EY>(cur[0], cur[1], cur[2], cur[3], lL1, lL3, up[0], up[2], uLL3, gcL, gr, g, c);
+}
+
+template <typename V>
+__device__ __forceinline__ void local_row(V (&r)[8], int what, float c) {
+#pragma unroll
+    for (int b = 0; b < 8; b += 4) {
+        if (what == 1) {
+            r[b + 1] = fmaf(c, r[b + 0], r[b + 1]);
+            r[b + 3] = fmaf(c, r[b + 2], r[b + 3]);
+            r[b + 2] = fmaf(c, r[b + 0], r[b + 2]);
+            r[b + 3] = fmaf(c, r[b + 1], r[b + 3]);
+        } else if (what == 2) {
+            r[b + 0] = fmaf(c, r[b + 1], r[b + 0]);
+            r[b + 2] = fmaf(c, r[b + 3], r[b + 2]);
+            r[b + 0] = fmaf(c, r[b + 2], r[b + 0]);
+            r[b + 1] = fmaf(c, r[b + 3], r[b + 1]);
+        }
+    }
+}
+
+// All steps of one iteration (newest row i), step k onward.
+template <class PR, int k, bool EX, bool EY, typename V, int NWIN>
+__device__ __forceinline__ void steps_from(V (&win)[NWIN][8], V (&sv)[PR::N][4], int i, int gcL, const Geo& g) {
+    if constexpr (k < PR::N) {
+        constexpr StepSpec st = PR::kSteps[k];
+        constexpr int lag = step_lag<PR>(k);
+        const int gr = i - lag;
+        if constexpr (st.plus) {
+            plus_row<st.kind, EX, EY>(win[lag], win[lag - 1], gcL, gr, g, st.c);
+        } else {
+            // x2, x3 of this row before its update, for the next row's update
+            const V s0 = win[lag][2], s1 = win[lag][6], s2 = win[lag][3], s3 = win[lag][7];
+            minus_row<st.kind, EX, EY>(win[lag], sv[k], gcL, gr, g, st.c);
+            sv[k][0] = s0;
+            sv[k][1] = s1;
+            sv[k][2] = s2;
+            sv[k][3] = s3;
+        }
+        if constexpr (st.after != 0) local_row(win[lag], st.after, st.ca);
+        steps_from<PR, k + 1, EX, EY>(win, sv, i, gcL, g);
+    }
+}
+
+// Raw block row `row` of the input into r (zeros outside the image).
+template <int DIR, typename T>
+__device__ __forceinline__ void stream_load(typename St<T>::V (&r)[8], const LevelParams& P, const Geo& g, int row) {
+    using V = typename St<T>::V;
+    const bool vec = P.vec != 0;
+    if constexpr (DIR == kForward) {
+        const T* in = static_cast<const T*>(P.in);
+        load4<T, true>(in, P.in_pitch, 2 * row, 2 * g.gcL, P.h, P.w, vec, r[0], r[1], r[4], r[5]);
+        load4<T, true>(in, P.in_pitch, 2 * row + 1, 2 * g.gcL, P.h, P.w, vec, r[2], r[3], r[6], r[7]);
+    } else {
+        const T* ll = static_cast<const T*>(P.in_ll);
+        const T* det = static_cast<const T*>(P.in);
+        const bool rE = row >= 0 && row < g.nEr;
+        const bool rO = row >= 0 && row < g.nOr;
+        const int64_t gre = rE ? row : 0, gro = rO ? row : 0;
+        load2<T, true>(ll + gre * P.in_ll_pitch, g.gcL, g.nEc, rE, vec, r[0], r[4]);
+        load2<T, true>(det + gre * P.in_pitch + g.nEc, g.gcL, g.nOc, rE, vec, r[1], r[5]);
+        load2<T, true>(det + (g.nEr + gro) * P.in_pitch, g.gcL, g.nEc, rO, vec, r[2], r[6]);
+        load2<T, true>(det + (g.nEr + gro) * P.in_pitch + g.nEc, g.gcL, g.nOc, rO, vec, r[3], r[7]);
+        (void)sizeof(V);
+    }
+}
+
+// Final block row gr to the output (core lanes only).
+template <int DIR, typename T, class PR>
+__device__ __forceinline__ void stream_store(const typename St<T>::V (&r)[8], const LevelParams& P, const Geo& g,
+                                             int gr) {
+    const bool vec = P.vec != 0;
+    if constexpr (DIR == kForward) {
+        T* ll = static_cast<T*>(P.out_ll);
+        T* det = static_cast<T*>(P.out);
+        using V = typename St<T>::V;
+        V l0 = r[0], l1 = r[4], h0 = r[3], h1 = r[7];
+        if constexpr (PR::kPostScale) {
+            l0 *= PR::kPost0; l1 *= PR::kPost0;
+            h0 *= PR::kPost3; h1 *= PR::kPost3;
+        }
+        store2<T, true>(ll + (int64_t)gr * P.out_ll_pitch, g.gcL, g.nEc, vec, l0, l1);
+        store2<T, true>(det + (int64_t)gr * P.out_pitch + g.nEc, g.gcL, g.nOc, vec, r[1], r[5]);
+        if (gr < g.nOr) {
+            store2<T, true>(det + (int64_t)(g.nEr + gr) * P.out_pitch, g.gcL, g.nEc, vec, r[2], r[6]);
+            store2<T, true>(det + (int64_t)(g.nEr + gr) * P.out_pitch + g.nEc, g.gcL, g.nOc, vec, h0, h1);
+        }
+    } else {
+        T* img = static_cast<T*>(P.out);
+        const int c = 2 * g.gcL;
+        store4<T, true>(img, P.out_pitch, 2 * gr, c, P.h, P.w, vec, r[0], r[1], r[4], r[5]);
+        store4<T, true>(img, P.out_pitch, 2 * gr + 1, c, P.h, P.w, vec, r[2], r[3], r[6], r[7]);
+    }
+}
+
+template <int DIR, int WAV, typename T, bool SPLIT, bool EX, int PF>
+__device__ __forceinline__ void stream_segment(const LevelParams& P, const Geo& g, int lane, int s0, int s1) {
+    using V = typename St<T>::V;
+    using PR = Prog<DIR, WAV, SPLIT>;
+    constexpr int LAGMAX = max_lag<PR>();
+    constexpr int NWIN = LAGMAX + 1;
+    const bool core_lane = lane >= kHalo / 2 && lane < kLanes - kHalo / 2;
+    const int i0 = s0 - kHalo;
+    const int i1 = s1 + LAGMAX;                   // one past the last iteration
+    V win[NWIN][8];
+    V sv[PR::N][4];
+    V ring[PF][8];
+#pragma unroll
+    for (int j = 0; j < NWIN; ++j)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) win[j][q] = V(0);
+#pragma unroll
+    for (int j = 0; j < PR::N; ++j) sv[j][0] = sv[j][1] = sv[j][2] = sv[j][3] = V(0);
+#pragma unroll
+    for (int u = 0; u < PF; ++u) stream_load<DIR, T>(ring[u], P, g, i0 + u < i1 ? i0 + u : -1);
+
+    for (int base = i0; base < i1; base += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int i = base + u;
+            if (i < i1) {
+#pragma unroll
+                for (int j = NWIN - 1; j > 0; --j)
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) win[j][q] = win[j - 1][q];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) win[0][q] = ring[u][q];
+                stream_load<DIR, T>(ring[u], P, g, i + PF < i1 ? i + PF : -1);
+                if constexpr (PR::kPreScale) {
+                    win[0][0] *= PR::kPre0; win[0][4] *= PR::kPre0;
+                    win[0][3] *= PR::kPre3; win[0][7] *= PR::kPre3;
+                }
+                if constexpr (PR::kPreLocal != 0) local_row(win[0], PR::kPreLocal, PR::kPreLocalC);
+                // rows whose neighbour indices need clamping: the first and the last rows of the image
+                const bool ey = i < 3 || i >= g.nOr - 1;
+                if (ey) steps_from<PR, 0, EX, true>(win, sv, i, g.gcL, g);
+                else steps_from<PR, 0, EX, false>(win, sv, i, g.gcL, g);
+                const int gr = i - LAGMAX;
+                if (core_lane && gr >= s0 && gr < s1) stream_store<DIR, T, PR>(win[LAGMAX], P, g, gr);
+            }
+        }
+    }
+}
+
+template <int DIR, int WAV, typename T, bool SPLIT, int W, int PF>
+__global__ void __launch_bounds__(W * kLanes) stream_kernel(LevelParams P) {
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+    // consecutive work-groups of one XCD take vertically adjacent segments,
+    // so the rows a segment re-reads from its neighbours are in that XCD's L2
+    const int nt = P.tiles_x * P.tiles_y;
+    const int per = (nt + 7) >> 3;
+    const int t = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if (t >= nt) return;
+    const int gx = t / P.tiles_y;
+    const int gy = t - gx * P.tiles_y;
+    Geo g;
+    g.nEr = (P.h + 1) >> 1; g.nOr = P.h >> 1;
+    g.nEc = (P.w + 1) >> 1; g.nOc = P.w >> 1;
+    const int nsx = (g.nEc + kStreamCoreBX - 1) / kStreamCoreBX;
+    const int sx = gx * W + wv;
+    if (sx >= nsx) return;                        // waves are independent: no barrier follows
+    const int cb0 = sx * kStreamCoreBX;
+    g.gcL = cb0 - kHalo + 2 * lane;
+    g.gr0 = 0;
+    const int s0 = gy * P.seg_rows;
+    const int s1 = min(s0 + P.seg_rows, g.nEr);
+    const bool ix = cb0 - kHalo >= 0 && cb0 + kStreamCoreBX + kHalo <= g.nOc;
+    const bool iy = s0 - kHalo >= 0 && s1 + kHalo <= g.nOr;
+    if (ix) {
+        if (SPLIT && iy) stream_segment<DIR, WAV, T, SPLIT, false, PF>(P, g, lane, s0, s1);
+        else stream_segment<DIR, WAV, T, false, false, PF>(P, g, lane, s0, s1);
+    } else {
+        stream_segment<DIR, WAV, T, false, true, PF>(P, g, lane, s0, s1);
+    }
+}
+
+
+}  // namespace kern
+}  // namespace dwt2

@@ -1,0 +1,90 @@
+"""Batched forward transform: one persistent launch over many uneven images.
+
+Every image of the batch must equal the single-image dwt2_fwd on that image
+bit for bit (same kernel configuration: the same tile arithmetic), and a
+sample of images is also checked against the CPU oracle.  The call is then
+captured in a graph and replayed several times, with eager work and
+synchronisations in between, each replay checked against the eager result.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import lifting
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1704_08657_amd as d  # noqa: E402
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def uneven(count, lo, hi, seed, odd=False):
+    shapes = workloads.uneven_shapes(count, lo, hi, seed)
+    if odd:  # make some sizes odd as well
+        shapes = [(h - (i % 2), w - ((i // 2) % 2)) for i, (h, w) in enumerate(shapes)]
+    rng = np.random.default_rng(seed)
+    return shapes, [rng.random(s, dtype=np.float32) for s in shapes]
+
+
+@pytest.mark.parametrize("tdt", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("config", [0, 1])
+def test_batched_equals_single(tdt, config):
+    shapes, imgs = uneven(24, 64, 700, seed=1, odd=True)
+    xs = [torch.from_numpy(x).to(dev()).to(tdt) for x in imgs]
+    lv = min(5, min(lifting.max_levels(*s) for s in shapes))
+    call = d.BatchedForward(xs, lv, config=config)
+    outs = call.run()
+    assert call.error_word() == 0
+    for x, y in zip(xs, outs):
+        ref = d.fwd(x, "cdf97", lv, config=config)
+        assert torch.equal(y, ref)
+
+
+def test_batched_split_and_oracle():
+    shapes, imgs = uneven(10, 64, 1500, seed=3)
+    xs = [torch.from_numpy(x).to(dev()) for x in imgs]
+    outs = d.fwd_batched(xs, levels=5, split=True)
+    for k in (0, 3, 7):
+        ref = lifting.fwd(imgs[k], "cdf97", 5)
+        got = outs[k].double().cpu().numpy()
+        assert np.abs(got - ref).max() / np.abs(ref).max() <= 1e-5
+
+
+def test_batched_many_small_images():
+    xs = [torch.from_numpy(x).to(dev()) for x in workloads.planes(1024, 256, 256, seed=2)]
+    outs = d.fwd_batched(xs, levels=5)
+    for k in (0, 511, 1023):
+        assert torch.equal(outs[k], d.fwd(xs[k], "cdf97", 5))
+
+
+def test_batched_graph_replay():
+    shapes, imgs = uneven(16, 64, 900, seed=5)
+    xs = [torch.from_numpy(x).to(dev()) for x in imgs]
+    call = d.BatchedForward(xs, 4)
+    call.run()
+    torch.cuda.synchronize()
+    eager = [y.clone() for y in call.outs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        call.run()                        # warm up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        call.run()
+    for rep in range(4):
+        for y in call.outs:
+            y.fill_(float("nan"))         # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for y, e in zip(call.outs, eager):
+            assert torch.equal(y, e), rep
+        assert call.error_word() == 0

@@ -212,11 +212,12 @@ def test_full_size_cdf53_crops(lv):
     assert torch.equal(xr.cpu(), torch.from_numpy(x))
 
 
-# ---- every tile shape computes the same values -----------------------------
+# ---- every kernel configuration computes the same values --------------------
 
-def test_tile_shapes_bit_identical():
+def test_kernel_configs_bit_identical():
     """Each coefficient's arithmetic does not depend on the tiling, so every
-    tile shape must give bit-identical results (a halo or race bug breaks it)."""
+    kernel configuration (tile shapes, streaming strips and segments) must
+    give bit-identical results (a halo, pipeline or race bug breaks it)."""
     cases = [("cdf97", torch.float32, (517, 1283), 3, False), ("cdf97", torch.float32, (1000, 700), 1, True),
              ("cdf97", torch.bfloat16, (300, 260), 2, False), ("cdf53", torch.int32, (613, 901), 4, False)]
     for wav, tdt, (h, w), lv, split in cases:
@@ -224,18 +225,18 @@ def test_tile_shapes_bit_identical():
             x = gpu(workloads.pixels_u8(h, w, seed=4))
         else:
             x = gpu(workloads.uniform(h, w, seed=4)).to(tdt)
-        ref_f = d.fwd(x, wav, lv, split=split, tile=0)
-        ref_i = d.inv(ref_f, wav, lv, split=split, tile=0)
-        for sh in range(1, d.DWT2_NUM_TILE_SHAPES):
-            say("tile shape", sh, wav, tdt, (h, w), lv, split)
-            f = d.fwd(x, wav, lv, split=split, tile=sh)
-            if split:   # the split runs only in tiles away from the border
+        ref_f = d.fwd(x, wav, lv, split=split, config=0)
+        ref_i = d.inv(ref_f, wav, lv, split=split, config=0)
+        for sh in range(1, d.DWT2_NUM_KERNEL_CONFIGS):
+            say("kernel config", sh, wav, tdt, (h, w), lv, split)
+            f = d.fwd(x, wav, lv, split=split, config=sh)
+            if split:   # the split runs only away from the border
                 assert rel_err(host(f), host(ref_f)) <= 1e-6
             else:
                 assert torch.equal(f, ref_f)
-                assert torch.equal(d.inv(f, wav, lv, tile=sh), ref_i)
+                assert torch.equal(d.inv(f, wav, lv, config=sh), ref_i)
         if wav == "cdf97" and tdt == torch.float32 and not split:
             g = ref_f
-            a0 = d.adj(g, lv, tile=0)
-            for sh in range(1, d.DWT2_NUM_TILE_SHAPES):
-                assert torch.equal(d.adj(g, lv, tile=sh), a0)
+            a0 = d.adj(g, lv, config=0)
+            for sh in range(1, d.DWT2_NUM_KERNEL_CONFIGS):
+                assert torch.equal(d.adj(g, lv, config=sh), a0)
