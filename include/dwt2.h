@@ -163,31 +163,31 @@ int dwt2_adj(const void* src, void* dst, int32_t height, int32_t width,
  * DWT2_OK or DWT2_E_FLAGS for an unknown index. */
 int dwt2_kernel_config(int index, int* algorithm, int* waves, int* rows, int* core_cols, int* core_rows);
 
-/* Device workspace (bytes) for dwt2_fwd_batched on these images: a work
- * table and two LL ping-pong buffers per image.  `images` is a host array. */
+/* Device workspace (bytes) for dwt2_fwd_batched on these images: the work
+ * tables (per level, each image's first tile; per image, the offset of its LL
+ * buffers) and two LL ping-pong buffers per image.  `images` is a host array.
+ * Returns a dwt2_status. */
 int dwt2_workspace_bytes_batched(const dwt2_image* images, int count, dwt2_dtype dtype, int levels,
                                  size_t* bytes);
 
-/* Batched forward CDF 9/7: `count` independent images of any (uneven) sizes,
- * every one transformed to `levels` levels, in one planner launch plus one
- * persistent launch on `stream` (each work-group takes tiles of any image and
- * level from a device work queue; a level waits only for the previous level
- * of the same image).  The images are given twice with identical contents:
- * `host_images` (host memory, used for the argument checks and the grid) and
- * `device_images` (device memory, read by the kernels), so the call performs
- * no copies or allocations and can be captured in a graph.  Float storage
- * (F32, BF16, F16); flags: DWT2_FLAG_SPLIT and a tile kernel configuration
- * (indices 0 or 1 of dwt2_kernel_config).  Every image's src and dst must not
- * overlap each other or the workspace.  Results equal dwt2_fwd on each image
+/* Batched forward CDF 9/7 (Section "Proposed Schemes", non-separable lifting,
+ * applied to each image as dwt2_fwd would): `count` independent images of any
+ * (uneven) sizes, every one transformed to `levels` levels, as one planner
+ * launch plus one launch per level on `stream`; the launch of a level covers
+ * the tiles of all images, so small images still fill the GPU.  The images
+ * are given twice with identical contents: `host_images` (host memory, used
+ * for the argument checks and the grid sizes) and `device_images` (device
+ * memory, read by the kernels; it must stay valid until the launches have
+ * run).  The call performs no copies or allocations and can be captured in a
+ * graph.  Float storage (F32, BF16, F16); flags: DWT2_FLAG_SPLIT and a tile
+ * kernel configuration (indices 0 or 1 of dwt2_kernel_config).  No image's
+ * src and dst may overlap each other or the workspace; distinct images must
+ * not share a dst.  The sum over the images of one level's tiles must stay
+ * below 2^31 (else DWT2_E_SHAPE).  Results equal dwt2_fwd on each image
  * (bit-identical for the same configuration). */
 int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_images, int count,
                      dwt2_dtype dtype, dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,
                      unsigned flags, void* workspace, size_t workspace_bytes, void* stream);
-
-/* Error word of a batched call's workspace header, read from a host copy of
- * the workspace's first 64 bytes: non-zero if a dependency wait gave up (the
- * results are then not valid).  Returns the word, or DWT2_E_NULL. */
-int dwt2_batched_error(const void* workspace_host_copy);
 
 /* Text of a dwt2_status. */
 const char* dwt2_status_string(int status);

@@ -52,7 +52,6 @@ SIGNATURES = {
     "dwt2_kernel_config": (_c_int, [_c_int] + [ctypes.POINTER(_c_int)] * 5),
     "dwt2_workspace_bytes_batched": (_c_int, [_c_p, _c_int, _c_int, _c_int, ctypes.POINTER(_c_sz)]),
     "dwt2_fwd_batched": (_c_int, [_c_p, _c_p, _c_int, _c_int, _c_int, _c_int, _c_int, _c_u, _c_p, _c_sz, _c_p]),
-    "dwt2_batched_error": (_c_int, [_c_p]),
     "dwt2_status_string": (ctypes.c_char_p, [_c_int]),
     "dwt2_last_hip_error": (ctypes.c_char_p, []),
 }
@@ -161,6 +160,16 @@ def workspace(h: int, w: int, levels: int, dtype, device):
     return torch.empty(n, dtype=torch.uint8, device=device)
 
 
+_DTYPE_NAMES = {DWT2_F32: "f32", DWT2_BF16: "bf16", DWT2_F16: "f16", DWT2_I32: "i32"}
+_DIRECTIONS = {"dwt2_fwd": "fwd", "dwt2_inv": "inv", "dwt2_adj": "adj"}
+
+
+def tuned_config(direction: str, wavelet: str, dtype: int, h: int, w: int, levels: int):
+    """Kernel configuration the autotuner recorded for this case, or None."""
+    from . import autotune
+    return autotune.lookup(direction, wavelet, _DTYPE_NAMES[dtype], h, w, levels)
+
+
 def _transform(fn, name, x, wavelet, levels, split, out, config=None):
     torch = _torch()
     _check(x)
@@ -179,6 +188,8 @@ def _transform(fn, name, x, wavelet, levels, split, out, config=None):
     ws_n = ws.numel() if ws is not None else 0
     stream = _stream_ptr(x2)
     flags = DWT2_FLAG_SPLIT if split else 0
+    if config is None:
+        config = tuned_config(_DIRECTIONS[name], wavelet, dt, H, W, levels)
     if config is not None:
         flags |= DWT2_FLAG_KERNEL(config)
     for i in range(x2.shape[0]):
@@ -233,6 +244,11 @@ class BatchedForward:
         self.outs = list(outs) if outs is not None else [torch.empty_like(x) for x in images]
         self.levels = levels
         self.dtype = dtype_code(images[0])
+        if config is None:
+            from . import autotune
+            config = autotune.load_cache().get(
+                f"{autotune.arch_name()}|batched|cdf97|{_DTYPE_NAMES[self.dtype]}|any|5") \
+                if autotune.load_cache() else None
         self.flags = (DWT2_FLAG_SPLIT if split else 0) | (DWT2_FLAG_KERNEL(config) if config is not None else 0)
         n = len(images)
         self.host = (dwt2_image * n)()
@@ -256,16 +272,10 @@ class BatchedForward:
             raise DWT2Error(st, "dwt2_fwd_batched")
         return self.outs
 
-    def error_word(self) -> int:
-        """Non-zero if a dependency wait of the last run gave up (synchronises)."""
-        head = self.workspace[:64].cpu().numpy().tobytes()
-        buf = ctypes.create_string_buffer(head, 64)
-        return lib().dwt2_batched_error(ctypes.cast(buf, ctypes.c_void_p))
-
 
 def fwd_batched(images, levels: int = 1, split: bool = False, config=None, outs=None):
-    """Forward CDF 9/7 of a list of [H, W] images of any sizes in one
-    persistent launch; returns the list of Mallat pyramids."""
+    """Forward CDF 9/7 of a list of [H, W] images of any sizes (one planner
+    launch plus one launch per level); returns the list of Mallat pyramids."""
     return BatchedForward(images, levels, split, config, outs).run()
 
 

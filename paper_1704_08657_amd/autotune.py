@@ -1,0 +1,153 @@
+"""Autotuner for the kernel configuration (tile shape / algorithm).
+
+Times every kernel configuration that the library offers for a case
+(direction, wavelet, storage type, image size class, level count) on the
+current GPU and records the fastest in a JSON cache.  The binding consults
+the cache when a call does not name a configuration; all configurations
+compute bit-identical results, so the choice affects speed only.
+
+    python -m paper_1704_08657_amd.autotune [--out FILE] [--quick]
+
+The cache key is "arch|direction|wavelet|dtype|size-class|levels"; the size
+class is the image side rounded up to a power of two (64 ... 16384).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE_PATH = os.path.join(HERE, "tuned_configs.json")
+BATCHED_CONFIGS = (0, 1)
+
+
+def size_class(h: int, w: int) -> int:
+    s = 64
+    while s < max(h, w) and s < 16384:
+        s *= 2
+    return s
+
+
+def key(arch: str, direction: str, wavelet: str, dtype: str, h: int, w: int, levels: int) -> str:
+    return f"{arch}|{direction}|{wavelet}|{dtype}|{size_class(h, w)}|{levels}"
+
+
+def arch_name() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+_cache = None
+
+
+def load_cache(path: str = CACHE_PATH) -> dict:
+    global _cache
+    if _cache is None:
+        try:
+            with open(path) as f:
+                _cache = json.load(f)
+        except (OSError, ValueError):
+            _cache = {}
+    return _cache
+
+
+def lookup(direction: str, wavelet: str, dtype: str, h: int, w: int, levels: int):
+    """Tuned configuration index for a case, or None."""
+    cache = load_cache()
+    if not cache:
+        return None
+    try:
+        arch = arch_name()
+    except Exception:
+        return None
+    return cache.get(key(arch, direction, wavelet, dtype, h, w, levels))
+
+
+def _time(torch, fn, steps=20, warm=4):
+    stream = torch.cuda.current_stream()
+    for i in range(warm):
+        fn(i)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for i in range(steps):
+        ev[i][0].record(stream)
+        fn(i)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in ev)
+    return ts[len(ts) // 2]
+
+
+def tune(sizes=(256, 1024, 4096, 8192), levels=(1, 5), quick=False, out=CACHE_PATH, log=print):
+    import torch
+    import paper_1704_08657_amd as d
+
+    dev = torch.device("cuda", 0)
+    arch = arch_name()
+    result = dict(load_cache(out)) if os.path.exists(out) else {}
+    dts = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16, "i32": torch.int32}
+    cases = []
+    for n in sizes:
+        for lv in levels:
+            for dt in (("f32", "bf16") if quick else ("f32", "bf16", "f16")):
+                cases += [("fwd", "cdf97", dt, n, lv), ("inv", "cdf97", dt, n, lv)]
+                if dt == "f32":
+                    cases.append(("adj", "cdf97", dt, n, lv))
+            cases += [("fwd", "cdf53", "i32", n, lv), ("inv", "cdf53", "i32", n, lv)]
+    nconf = d.DWT2_NUM_KERNEL_CONFIGS
+    for direction, wav, dt, n, lv in cases:
+        g = torch.Generator(device=dev).manual_seed(0)
+        if dt == "i32":
+            xs = [torch.randint(0, 256, (n, n), device=dev, dtype=torch.int32, generator=g) for _ in range(2)]
+        else:
+            xs = [torch.rand((n, n), device=dev, generator=g).to(dts[dt]) for _ in range(2)]
+        ys = [torch.empty_like(x) for x in xs]
+        fn = {"fwd": lambda x, y, c: d.fwd(x, wav, lv, out=y, config=c),
+              "inv": lambda x, y, c: d.inv(x, wav, lv, out=y, config=c),
+              "adj": lambda x, y, c: d.adj(x, lv, out=y, config=c)}[direction]
+        best, best_ms = None, float("inf")
+        for c in range(nconf):
+            ms = _time(torch, lambda i: fn(xs[i % 2], ys[i % 2], c), steps=8 if quick else 20)
+            if ms < best_ms:
+                best, best_ms = c, ms
+        k = key(arch, direction, wav, dt, n, n, lv)
+        result[k] = best
+        log(f"{k}: config {best} ({best_ms * 1e3:.1f} us)")
+    # batched: between the configurations the batched kernels support
+    for dt in ("f32", "bf16"):
+        shapes = [(int(h), int(w)) for h, w in zip(*[iter(
+            torch.randint(32, 2049, (64,), generator=torch.Generator().manual_seed(1)).mul(2).tolist())] * 2)]
+        imgs = [torch.rand(s, device=dev).to(dts[dt]) for s in shapes]
+        best, best_ms = None, float("inf")
+        for c in BATCHED_CONFIGS:
+            call = d.BatchedForward(imgs, 5, config=c)
+            ms = _time(torch, lambda i: call.run(), steps=5 if quick else 10, warm=2)
+            if ms < best_ms:
+                best, best_ms = c, ms
+        k = f"{arch}|batched|cdf97|{dt}|any|5"
+        result[k] = best
+        log(f"{k}: config {best} ({best_ms * 1e3:.1f} us)")
+    with open(out, "w") as f:
+        json.dump(result, f, indent=1, sort_keys=True)
+    global _cache
+    _cache = result
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=CACHE_PATH)
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--sizes", default="256,1024,4096,8192")
+    a = ap.parse_args()
+    t0 = time.time()
+    tune(sizes=tuple(int(s) for s in a.sizes.split(",")), quick=a.quick, out=a.out,
+         log=lambda s: print(s, flush=True))
+    print(f"tuned in {time.time() - t0:.1f} s -> {a.out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -326,7 +326,7 @@ int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_ima
     if (!dwt2::batched_config_supported(cfg)) return DWT2_E_FLAGS;
     const size_t es = elem_size(dtype);
     const int core = dwt2::core_rows(dwt2::kConfigs[cfg]);
-    uint64_t tickets = 0;
+    uint64_t tiles[32] = {0};
     for (int i = 0; i < count; ++i) {
         const dwt2_image& im = host_images[i];
         if (!im.src || !im.dst) return DWT2_E_NULL;
@@ -336,9 +336,13 @@ int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_ima
         if (ranges_overlap(im.src, span_bytes(im.height, im.width, im.src_pitch, es), im.dst,
                            span_bytes(im.height, im.width, im.dst_pitch, es)))
             return DWT2_E_ALIAS;
-        for (int l = 0; l < levels; ++l) tickets += dwt2::level_chunks(im.height, im.width, l, core);
+        for (int l = 0; l < levels; ++l) tiles[l] += dwt2::level_tile_count(im.height, im.width, l, core);
     }
-    if (tickets >= 0xffffffffull) return DWT2_E_SHAPE;
+    uint32_t tiles_per_level[32];
+    for (int l = 0; l < levels; ++l) {
+        if (tiles[l] > 0x7ffffff8ull) return DWT2_E_SHAPE;     // grid of one launch
+        tiles_per_level[l] = (uint32_t)tiles[l];
+    }
     size_t need = 0;
     const int st = dwt2_workspace_bytes_batched(host_images, count, dtype, levels, &need);
     if (st) return st;
@@ -350,12 +354,7 @@ int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_ima
             return DWT2_E_ALIAS;
     }
     return report(dwt2::launch_fwd_batched(to_dtype(dtype), (flags & DWT2_FLAG_SPLIT) != 0, cfg, device_images,
-                                           count, levels, workspace, (uint32_t)tickets, (hipStream_t)stream));
-}
-
-int dwt2_batched_error(const void* workspace_host_copy) {
-    if (!workspace_host_copy) return DWT2_E_NULL;
-    return (int)static_cast<const dwt2::BatchHeader*>(workspace_host_copy)->error;
+                                           count, levels, workspace, tiles_per_level, (hipStream_t)stream));
 }
 
 const char* dwt2_status_string(int status) {

@@ -71,11 +71,12 @@ struct LevelParams {
 hipError_t launch_level(Direction dir, Wavelet wav, Dtype dt, bool split, int cfg,
                         const LevelParams& p, hipStream_t stream);
 
-// Batched forward CDF 9/7 (planner + persistent kernel) for tile
-// configurations `cfg` with batched_config_supported(cfg).  `tickets` is the
-// total number of work chunks (bounds the persistent grid).
+// Batched forward CDF 9/7 (planner + one launch per level) for tile
+// configurations `cfg` with batched_config_supported(cfg).
+// `tiles_per_level[l]` (host array of `levels` entries) is the number of
+// tiles of level l summed over the images: it sizes that level's grid.
 bool batched_config_supported(int cfg);
 hipError_t launch_fwd_batched(Dtype dt, bool split, int cfg, const dwt2_image* dev_imgs, int count, int levels,
-                              void* ws, uint32_t tickets, hipStream_t s);
+                              void* ws, const uint32_t* tiles_per_level, hipStream_t s);
 
 }  // namespace dwt2

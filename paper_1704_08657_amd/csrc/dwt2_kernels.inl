@@ -102,6 +102,21 @@ __device__ __forceinline__ float from_left(float v) {
 }
 __device__ __forceinline__ int from_right(int v) { return dpp_from_right(v); }
 __device__ __forceinline__ int from_left(int v) { return dpp_from_left(v); }
+// Same shifts, but the lane without a source lane (63 for from_right, 0 for
+// from_left) keeps `old` instead (bound_ctrl off): one instruction replaces a
+// shift plus a lane select.
+__device__ __forceinline__ float from_right_or(float old, float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_left_or(float old, float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ int from_right_or(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, 0x130, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int from_left_or(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false);
+}
 
 // ---------------------------------------------------------------------------
 // geometry of one tile as seen by one lane
@@ -291,58 +306,68 @@ template <typename V> struct PlusOps { V x0R[4], x2R[4], x0D[4], x1D[4], x0DR[4]
 // Operands of an update-shaped step: left (x1l, x3l), upper (x2u, x3u), upper-left (x3ul).
 template <typename V> struct MinusOps { V x1l[4], x3l[4], x2u[4], x3u[4], x3ul[4]; };
 
-// cur: the row; dn: the row below (x0, x1 used); dnRL0: the right lane's L.x0 of the row below.
+// cur: the row; dn: the row below (x0, x1 used); dnRL0: the right lane's L.x0
+// of the row below (E0.x0 in lane 63).  The right neighbour of R is the next
+// lane's L, or E0 in lane 63; the right neighbour of E1 is L (block -1 -> 0 in
+// lane 0; in lane 63, block 129 is outermost halo and any value will do).
 template <typename V>
 __device__ __forceinline__ void gather_plus(const V (&cur)[kBX], const V (&dn)[kBX], V dnRL0, LaneRole lr,
                                             PlusOps<V>& o) {
-    const V rL0 = from_right(cur[kL + 0]);
-    const V rL2 = from_right(cur[kL + 2]);
+    (void)lr;
     o.x0R[0] = cur[kR + 0]; o.x2R[0] = cur[kR + 2];                          // L -> R
     o.x0D[0] = dn[kL + 0]; o.x1D[0] = dn[kL + 1]; o.x0DR[0] = dn[kR + 0];
-    o.x0R[1] = lr.l63 ? cur[kE0 + 0] : rL0;                                  // R -> next lane's L
-    o.x2R[1] = lr.l63 ? cur[kE0 + 2] : rL2;                                  //      (E0 in lane 63)
-    o.x0D[1] = dn[kR + 0]; o.x1D[1] = dn[kR + 1]; o.x0DR[1] = lr.l63 ? dn[kE0 + 0] : dnRL0;
+    o.x0R[1] = from_right_or(cur[kE0 + 0], cur[kL + 0]);                     // R -> next lane's L
+    o.x2R[1] = from_right_or(cur[kE0 + 2], cur[kL + 2]);
+    o.x0D[1] = dn[kR + 0]; o.x1D[1] = dn[kR + 1]; o.x0DR[1] = dnRL0;
     o.x0R[2] = cur[kE1 + 0]; o.x2R[2] = cur[kE1 + 2];                        // E0 -> E1
     o.x0D[2] = dn[kE0 + 0]; o.x1D[2] = dn[kE0 + 1]; o.x0DR[2] = dn[kE1 + 0];
-    o.x0R[3] = lr.l0 ? cur[kL + 0] : cur[kE1 + 0];                           // E1 -> L in lane 0
-    o.x2R[3] = lr.l0 ? cur[kL + 2] : cur[kE1 + 2];                           //   (outermost halo otherwise)
-    o.x0D[3] = dn[kE1 + 0]; o.x1D[3] = dn[kE1 + 1]; o.x0DR[3] = lr.l0 ? dn[kL + 0] : dn[kE1 + 0];
+    o.x0R[3] = cur[kL + 0]; o.x2R[3] = cur[kL + 2];                          // E1 -> L
+    o.x0D[3] = dn[kE1 + 0]; o.x1D[3] = dn[kE1 + 1]; o.x0DR[3] = dn[kL + 0];
 }
 
-// cur: the row; up: the row above (x2, x3 used); upLR3: the left lane's R.x3 of the row above.
+// cur: the row; up: the row above (x2, x3 used); upLR3: the left lane's R.x3
+// of the row above (E1.x3 in lane 0).  The left neighbour of L is the
+// previous lane's R, or E1 in lane 0; the left neighbour of E0 is R (block
+// 128 -> 127 in lane 63; in lane 0, block -2 is outermost halo).
 template <typename V>
 __device__ __forceinline__ void gather_minus(const V (&cur)[kBX], const V (&up)[kBX], V upLR3, LaneRole lr,
                                              MinusOps<V>& o) {
-    const V lR1 = from_left(cur[kR + 1]);
-    const V lR3 = from_left(cur[kR + 3]);
-    o.x1l[0] = lr.l0 ? cur[kE1 + 1] : lR1;                                   // L <- previous lane's R
-    o.x3l[0] = lr.l0 ? cur[kE1 + 3] : lR3;                                   //      (E1 in lane 0)
-    o.x2u[0] = up[kL + 2]; o.x3u[0] = up[kL + 3]; o.x3ul[0] = lr.l0 ? up[kE1 + 3] : upLR3;
+    (void)lr;
+    o.x1l[0] = from_left_or(cur[kE1 + 1], cur[kR + 1]);                      // L <- previous lane's R
+    o.x3l[0] = from_left_or(cur[kE1 + 3], cur[kR + 3]);
+    o.x2u[0] = up[kL + 2]; o.x3u[0] = up[kL + 3]; o.x3ul[0] = upLR3;
     o.x1l[1] = cur[kL + 1]; o.x3l[1] = cur[kL + 3];                          // R <- L
     o.x2u[1] = up[kR + 2]; o.x3u[1] = up[kR + 3]; o.x3ul[1] = up[kL + 3];
-    o.x1l[2] = lr.l63 ? cur[kR + 1] : cur[kE0 + 1];                          // E0 <- R in lane 63
-    o.x3l[2] = lr.l63 ? cur[kR + 3] : cur[kE0 + 3];                          //   (outermost halo otherwise)
-    o.x2u[2] = up[kE0 + 2]; o.x3u[2] = up[kE0 + 3]; o.x3ul[2] = lr.l63 ? up[kR + 3] : up[kE0 + 3];
+    o.x1l[2] = cur[kR + 1]; o.x3l[2] = cur[kR + 3];                          // E0 <- R
+    o.x2u[2] = up[kE0 + 2]; o.x3u[2] = up[kE0 + 3]; o.x3ul[2] = up[kR + 3];
     o.x1l[3] = cur[kE0 + 1]; o.x3l[3] = cur[kE0 + 3];                        // E1 <- E0
     o.x2u[3] = up[kE1 + 2]; o.x3u[3] = up[kE1 + 3]; o.x3ul[3] = up[kE0 + 3];
 }
 
-template <int KIND, bool EX, bool EY, typename V>
+// EMASK selects the halo blocks a step must update (bit 0: E0, bit 1: E1).
+// Going backwards from the 128 output columns, a predict-shaped step widens
+// the columns the previous stage must provide by one to the right, an
+// update-shaped step by one to the left; a halo block is updated only at the
+// steps whose stage is needed at its column (-2, -1 in lane 0; 128, 129 in
+// lane 63).  Skipped halo values are never read by a needed value.
+template <int KIND, int EMASK, bool EX, bool EY, typename V>
 __device__ __forceinline__ void apply_plus(V (&cur)[kBX], const PlusOps<V>& o, const int (&gc)[4], int gr,
                                            const Geo& g, float c) {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-        plus_block<KIND, EX, EY>(cur[4 * b], cur[4 * b + 1], cur[4 * b + 2], cur[4 * b + 3], o.x0R[b], o.x2R[b],
-                                 o.x0D[b], o.x1D[b], o.x0DR[b], gc[b], gr, g, c);
+        if (b < 2 || (EMASK >> (b - 2)) & 1)
+            plus_block<KIND, EX, EY>(cur[4 * b], cur[4 * b + 1], cur[4 * b + 2], cur[4 * b + 3], o.x0R[b],
+                                     o.x2R[b], o.x0D[b], o.x1D[b], o.x0DR[b], gc[b], gr, g, c);
 }
 
-template <int KIND, bool EX, bool EY, typename V>
+template <int KIND, int EMASK, bool EX, bool EY, typename V>
 __device__ __forceinline__ void apply_minus(V (&cur)[kBX], const MinusOps<V>& o, const int (&gc)[4], int gr,
                                             const Geo& g, float c) {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-        minus_block<KIND, EX, EY>(cur[4 * b], cur[4 * b + 1], cur[4 * b + 2], cur[4 * b + 3], o.x1l[b], o.x3l[b],
-                                  o.x2u[b], o.x3u[b], o.x3ul[b], gc[b], gr, g, c);
+        if (b < 2 || (EMASK >> (b - 2)) & 1)
+            minus_block<KIND, EX, EY>(cur[4 * b], cur[4 * b + 1], cur[4 * b + 2], cur[4 * b + 3], o.x1l[b],
+                                      o.x3l[b], o.x2u[b], o.x3u[b], o.x3ul[b], gc[b], gr, g, c);
 }
 
 // Edge rows exchanged between the waves of a tile: x0, x1 of the top row (read
@@ -363,14 +388,14 @@ __device__ __forceinline__ void publish_bottom(V (&a)[K][kBX], Edge8<V> (*buf)[k
 
 // Predict-shaped step over the tile: rows top to bottom, so row r+1 is still
 // unmodified when row r reads it.
-template <int KIND, bool EDGE, int NW, int K, typename V>
+template <int KIND, int EMASK, bool EDGE, int NW, int K, typename V>
 __device__ __forceinline__ void plus_step(V (&a)[K][kBX], Edge8<V> (*buf)[kLanes], int lane, int wv,
                                           const Geo& g, const int (&gc)[4], LaneRole lr, float c) {
 #pragma unroll
     for (int r = 0; r < K; ++r) {
         PlusOps<V> o;
         if (r + 1 < K) {
-            gather_plus(a[r], a[r + 1], from_right(a[r + 1][kL + 0]), lr, o);
+            gather_plus(a[r], a[r + 1], from_right_or(a[r + 1][kE0 + 0], a[r + 1][kL + 0]), lr, o);
         } else {
             V dn[kBX];
             V rl0;
@@ -378,27 +403,27 @@ __device__ __forceinline__ void plus_step(V (&a)[K][kBX], Edge8<V> (*buf)[kLanes
                 const Edge8<V> q = buf[wv + 1][lane];
                 dn[kL + 0] = q.m.a; dn[kL + 1] = q.m.b; dn[kR + 0] = q.m.c; dn[kR + 1] = q.m.d;
                 dn[kE0 + 0] = q.e.a; dn[kE0 + 1] = q.e.b; dn[kE1 + 0] = q.e.c; dn[kE1 + 1] = q.e.d;
-                rl0 = buf[wv + 1][lane < kLanes - 1 ? lane + 1 : lane].m.a;
+                rl0 = lane < kLanes - 1 ? buf[wv + 1][lane + 1].m.a : q.e.a;
             } else {                              // below the tile: halo, any finite value
 #pragma unroll
                 for (int q = 0; q < kBX; ++q) dn[q] = a[r][q];
-                rl0 = from_right(a[r][kL + 0]);
+                rl0 = from_right_or(a[r][kE0 + 0], a[r][kL + 0]);
             }
             gather_plus(a[r], dn, rl0, lr, o);
         }
-        apply_plus<KIND, EDGE, EDGE>(a[r], o, gc, g.gr0 + r, g, c);
+        apply_plus<KIND, EMASK, EDGE, EDGE>(a[r], o, gc, g.gr0 + r, g, c);
     }
 }
 
 // Update-shaped step over the tile: rows bottom to top.
-template <int KIND, bool EDGE, int NW, int K, typename V>
+template <int KIND, int EMASK, bool EDGE, int NW, int K, typename V>
 __device__ __forceinline__ void minus_step(V (&a)[K][kBX], Edge8<V> (*buf)[kLanes], int lane, int wv,
                                            const Geo& g, const int (&gc)[4], LaneRole lr, float c) {
 #pragma unroll
     for (int r = K - 1; r >= 0; --r) {
         MinusOps<V> o;
         if (r > 0) {
-            gather_minus(a[r], a[r - 1], from_left(a[r - 1][kR + 3]), lr, o);
+            gather_minus(a[r], a[r - 1], from_left_or(a[r - 1][kE1 + 3], a[r - 1][kR + 3]), lr, o);
         } else {
             V up[kBX];
             V lr3;
@@ -406,15 +431,15 @@ __device__ __forceinline__ void minus_step(V (&a)[K][kBX], Edge8<V> (*buf)[kLane
                 const Edge8<V> q = buf[wv - 1][lane];
                 up[kL + 2] = q.m.a; up[kL + 3] = q.m.b; up[kR + 2] = q.m.c; up[kR + 3] = q.m.d;
                 up[kE0 + 2] = q.e.a; up[kE0 + 3] = q.e.b; up[kE1 + 2] = q.e.c; up[kE1 + 3] = q.e.d;
-                lr3 = buf[wv - 1][lane > 0 ? lane - 1 : 0].m.d;
+                lr3 = lane > 0 ? buf[wv - 1][lane - 1].m.d : q.e.d;
             } else {                              // above the tile: halo
 #pragma unroll
                 for (int q = 0; q < kBX; ++q) up[q] = a[r][q];
-                lr3 = from_left(a[r][kR + 3]);
+                lr3 = from_left_or(a[r][kE1 + 3], a[r][kR + 3]);
             }
             gather_minus(a[r], up, lr3, lr, o);
         }
-        apply_minus<KIND, EDGE, EDGE>(a[r], o, gc, g.gr0 + r, g, c);
+        apply_minus<KIND, EMASK, EDGE, EDGE>(a[r], o, gc, g.gr0 + r, g, c);
     }
 }
 
@@ -460,53 +485,57 @@ __device__ __forceinline__ void scale(V (&a)[K][kBX], float s0, float s3) {
 template <int DIR, int WAV, bool EDGE, bool SPLIT, int NW, int K, typename V>
 __device__ __forceinline__ void run(V (&a)[K][kBX], Edge8<V> (*bT)[kLanes], Edge8<V> (*bS)[kLanes],
                                     int lane, int wv, const Geo& g, const int (&gc)[4], LaneRole lr) {
-#define DWT2_PLUS(KIND_, c_) publish_top(a, bT, lane, wv); __syncthreads(); \
-    plus_step<KIND_, EDGE, NW>(a, bT, lane, wv, g, gc, lr, (c_));
-#define DWT2_MINUS(KIND_, c_) publish_bottom(a, bS, lane, wv); __syncthreads(); \
-    minus_step<KIND_, EDGE, NW>(a, bS, lane, wv, g, gc, lr, (c_));
+#define DWT2_PLUS(KIND_, M_, c_) publish_top(a, bT, lane, wv); __syncthreads(); \
+    plus_step<KIND_, M_, EDGE, NW>(a, bT, lane, wv, g, gc, lr, (c_));
+#define DWT2_MINUS(KIND_, M_, c_) publish_bottom(a, bS, lane, wv); __syncthreads(); \
+    minus_step<KIND_, M_, EDGE, NW>(a, bS, lane, wv, g, gc, lr, (c_));
+    // halo masks (E0 = 1, E1 = 2) per step, from the column ranges each stage
+    // must cover: predict/update/predict/update -> 3, 3, 2, 0;
+    // update/predict/update/predict -> 3, 3, 1, 0; predict/update -> 2, 0;
+    // update/predict -> 1, 0
     if constexpr (WAV == kCdf53) {
         if constexpr (DIR == kForward) {
-            DWT2_PLUS(kIntFwd, 0.f)
-            DWT2_MINUS(kIntFwd, 0.f)
+            DWT2_PLUS(kIntFwd, 2, 0.f)
+            DWT2_MINUS(kIntFwd, 0, 0.f)
         } else {
-            DWT2_MINUS(kIntInv, 0.f)
-            DWT2_PLUS(kIntInv, 0.f)
+            DWT2_MINUS(kIntInv, 1, 0.f)
+            DWT2_PLUS(kIntInv, 0, 0.f)
         }
     } else if constexpr (DIR == kForward) {
         if constexpr (SPLIT) {
             local_predict(a, kAlpha);
-            DWT2_PLUS(kSplit, kAlpha) local_update(a, kBeta);
-            DWT2_MINUS(kSplit, kBeta) local_predict(a, kGamma);
-            DWT2_PLUS(kSplit, kGamma) local_update(a, kDelta);
-            DWT2_MINUS(kSplit, kDelta)
+            DWT2_PLUS(kSplit, 3, kAlpha) local_update(a, kBeta);
+            DWT2_MINUS(kSplit, 3, kBeta) local_predict(a, kGamma);
+            DWT2_PLUS(kSplit, 2, kGamma) local_update(a, kDelta);
+            DWT2_MINUS(kSplit, 0, kDelta)
         } else {
-            DWT2_PLUS(kFloat, kAlpha)
-            DWT2_MINUS(kFloat, kBeta)
-            DWT2_PLUS(kFloat, kGamma)
-            DWT2_MINUS(kFloat, kDelta)
+            DWT2_PLUS(kFloat, 3, kAlpha)
+            DWT2_MINUS(kFloat, 3, kBeta)
+            DWT2_PLUS(kFloat, 2, kGamma)
+            DWT2_MINUS(kFloat, 0, kDelta)
         }
         scale(a, kZeta2, kZetaM2);
     } else if constexpr (DIR == kInverse) {
         scale(a, kZetaM2, kZeta2);
         if constexpr (SPLIT) {
-            DWT2_MINUS(kSplit, -kDelta) local_update(a, -kDelta);
-            DWT2_PLUS(kSplit, -kGamma) local_predict(a, -kGamma);
-            DWT2_MINUS(kSplit, -kBeta) local_update(a, -kBeta);
-            DWT2_PLUS(kSplit, -kAlpha) local_predict(a, -kAlpha);
+            DWT2_MINUS(kSplit, 3, -kDelta) local_update(a, -kDelta);
+            DWT2_PLUS(kSplit, 3, -kGamma) local_predict(a, -kGamma);
+            DWT2_MINUS(kSplit, 1, -kBeta) local_update(a, -kBeta);
+            DWT2_PLUS(kSplit, 0, -kAlpha) local_predict(a, -kAlpha);
         } else {
-            DWT2_MINUS(kFloat, -kDelta)
-            DWT2_PLUS(kFloat, -kGamma)
-            DWT2_MINUS(kFloat, -kBeta)
-            DWT2_PLUS(kFloat, -kAlpha)
+            DWT2_MINUS(kFloat, 3, -kDelta)
+            DWT2_PLUS(kFloat, 3, -kGamma)
+            DWT2_MINUS(kFloat, 1, -kBeta)
+            DWT2_PLUS(kFloat, 0, -kAlpha)
         }
     } else {
         // W^T = T_1^T S_1^T T_2^T S_2^T Z: transposed steps in reverse order;
         // the transpose of an update is predict-shaped and vice versa.
         scale(a, kZeta2, kZetaM2);
-        DWT2_PLUS(kAdj, kDelta)
-        DWT2_MINUS(kAdj, kGamma)
-        DWT2_PLUS(kAdj, kBeta)
-        DWT2_MINUS(kAdj, kAlpha)
+        DWT2_PLUS(kAdj, 3, kDelta)
+        DWT2_MINUS(kAdj, 3, kGamma)
+        DWT2_PLUS(kAdj, 2, kBeta)
+        DWT2_MINUS(kAdj, 0, kAlpha)
     }
 #undef DWT2_PLUS
 #undef DWT2_MINUS
@@ -636,8 +665,10 @@ __device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][kBX], const 
                            a[r][kR + 1]);
             load4<T, EDGE>(in, P.in_pitch, row + 1, 2 * g.gcL, P.h, P.w, vec, a[r][kL + 2], a[r][kL + 3],
                            a[r][kR + 2], a[r][kR + 3]);
-            a[r][kE0 + 0] = a[r][kE0 + 1] = a[r][kE1 + 0] = a[r][kE1 + 1] = V(0);
-            a[r][kE0 + 2] = a[r][kE0 + 3] = a[r][kE1 + 2] = a[r][kE1 + 3] = V(0);
+            if (EDGE) {
+                a[r][kE0 + 0] = a[r][kE0 + 1] = a[r][kE1 + 0] = a[r][kE1 + 1] = V(0);
+                a[r][kE0 + 2] = a[r][kE0 + 3] = a[r][kE1 + 2] = a[r][kE1 + 3] = V(0);
+            }
             if (halo_lane) {
                 load4<T, EDGE>(in, P.in_pitch, row, 2 * gcE0, P.h, P.w, vec, a[r][kE0 + 0], a[r][kE0 + 1],
                                a[r][kE1 + 0], a[r][kE1 + 1]);
@@ -662,8 +693,10 @@ __device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][kBX], const 
             load2<T, EDGE>(p1, g.gcL, g.nOc, rE, vec, a[r][kL + 1], a[r][kR + 1]);
             load2<T, EDGE>(p2, g.gcL, g.nEc, rO, vec, a[r][kL + 2], a[r][kR + 2]);
             load2<T, EDGE>(p3, g.gcL, g.nOc, rO, vec, a[r][kL + 3], a[r][kR + 3]);
+            if (EDGE) {
 #pragma unroll
-            for (int q = kE0; q < kBX; ++q) a[r][q] = V(0);
+                for (int q = kE0; q < kBX; ++q) a[r][q] = V(0);
+            }
             if (halo_lane) {
                 load2<T, EDGE>(p0, gcE0, g.nEc, rE, vec, a[r][kE0 + 0], a[r][kE1 + 0]);
                 load2<T, EDGE>(p1, gcE0, g.nOc, rE, vec, a[r][kE0 + 1], a[r][kE1 + 1]);

@@ -1,0 +1,81 @@
+// Host check of the batched work plan (dwt2_batch_plan.h): on random batches
+// of uneven images, every tile of every image at every level is covered
+// exactly once by the per-level grids (with the XCD remap of the batched
+// level kernel), the work tables fit below the LL area, and every
+// intermediate LL band read or written stays inside its own buffer.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+#include <cstdint>
+#include <algorithm>
+#include <random>
+#include "dwt2_batch_plan.h"
+using namespace dwt2;
+int run(const std::vector<int>& H, const std::vector<int>& W, int levels, int core, size_t es) {
+    int count = H.size(); int bad = 0;
+    BatchLayout L = batch_layout(count, levels);
+    std::vector<uint32_t> off((size_t)levels * (count + 1));
+    for (int l = 0; l < levels; ++l) {
+        uint32_t c = 0;
+        for (int i = 0; i < count; ++i) { off[l*(count+1)+i] = c; c += (uint32_t)level_tile_count(H[i], W[i], l, core); }
+        off[l*(count+1)+count] = c;
+    }
+    size_t llsum = 0; std::vector<size_t> llo(count);
+    for (int i = 0; i < count; ++i) { llo[i] = llsum; llsum += image_ll_bytes(H[i], W[i], levels, es); }
+    // tables inside workspace before LL area
+    if (L.off_tile + sizeof(uint32_t)*off.size() > L.off_ll_off) bad++;
+    if (L.off_ll_off + 8*(size_t)count > L.off_ll) bad++;
+    for (int l = 0; l < levels; ++l) {
+        uint32_t total = off[l*(count+1)+count];
+        uint32_t grid = (total + 7) / 8 * 8; uint32_t per = grid >> 3;
+        std::vector<std::vector<int>> seen(count);
+        for (int i = 0; i < count; ++i) seen[i].assign(level_tile_count(H[i], W[i], l, core), 0);
+        for (uint32_t b = 0; b < grid; ++b) {
+            uint32_t t = (b & 7) * per + (b >> 3);
+            if (t >= total) continue;
+            const uint32_t* o = &off[l*(count+1)];
+            int lo = 0, hi = count;
+            while (hi - lo > 1) { int mid = (lo+hi)>>1; if (o[mid] <= t) lo = mid; else hi = mid; }
+            int tt = t - o[lo];
+            if (tt < 0 || tt >= (int)seen[lo].size()) { bad++; continue; }
+            seen[lo][tt]++;
+            // buffer bounds: in / out_ll of this level inside the LL area
+            int32_t hl, wl; level_size(H[lo], W[lo], l, &hl, &wl);
+            size_t A = llo[lo], B = A + image_ll_b_offset(H[lo], W[lo], levels, es);
+            size_t endimg = llo[lo] + image_ll_bytes(H[lo], W[lo], levels, es);
+            if (l > 0) {  // input: hl rows of wl elements at pitch ll_pitch(wl)
+                size_t base = (l-1)%2==0 ? A : B;
+                size_t lastend = base + ((size_t)(hl-1)*ll_pitch(wl) + wl) * es;
+                if (lastend > endimg || (((l-1)%2==0) && lastend > B)) { printf("in oob l=%d i=%d\n", l, lo); bad++; }
+            }
+            if (l + 1 < levels) {
+                size_t base = l%2==0 ? A : B;
+                int32_t ho = (hl+1)/2, wo = (wl+1)/2;
+                size_t lastend = base + ((size_t)(ho-1)*ll_pitch(wo) + wo) * es;
+                if (lastend > endimg || ((l%2==0) && lastend > B)) { printf("out oob l=%d i=%d\n", l, lo); bad++; }
+            }
+        }
+        for (int i = 0; i < count; ++i) for (int v : seen[i]) if (v != 1) { bad++; break; }
+    }
+    return bad;
+}
+int main() {
+    std::mt19937 rng(7); int bad = 0, cases = 0;
+    for (int core : {12, 28}) for (size_t es : {2, 4}) for (int rep = 0; rep < 200; ++rep) {
+        int count = 1 + rng() % 300; std::vector<int> H(count), W(count);
+        int lo = 2 + rng() % 64, hi = lo + rng() % 3000;
+        for (int i = 0; i < count; ++i) { H[i] = lo + rng() % (hi - lo + 1); W[i] = lo + rng() % (hi - lo + 1); }
+        // largest level count for which every transformed level is at least 2 x 2
+        int ml = 30;
+        for (int i = 0; i < count; ++i) {
+            int m = 0; int32_t hl, wl;
+            for (;;) { level_size(H[i], W[i], m, &hl, &wl); if (hl < 2 || wl < 2) break; ++m; }
+            ml = std::min(ml, m);
+        }
+        if (ml < 1) continue;
+        int levels = 1 + rng() % ml;
+        bad += run(H, W, levels, core, es); ++cases;
+    }
+    printf("cases %d bad %d\n", cases, bad);
+    return bad != 0;
+}

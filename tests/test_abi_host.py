@@ -110,3 +110,47 @@ def test_tensor_api_refuses_cpu_tensors():
     torch = pytest.importorskip("torch")
     with pytest.raises(RuntimeError, match="GPU only"):
         d.fwd(torch.zeros(8, 8))
+
+
+def test_batched_argument_errors():
+    imgs = (d.dwt2_image * 2)()
+    imgs[0] = d.dwt2_image(FAKE_SRC, FAKE_DST, 64, 64, 64, 64)
+    imgs[1] = d.dwt2_image(FAKE_SRC + (1 << 24), FAKE_DST + (1 << 24), 100, 70, 70, 70)
+    L = d.lib()
+    hp = ctypes.cast(imgs, ctypes.c_void_p)
+    n = ctypes.c_size_t(0)
+    assert L.dwt2_workspace_bytes_batched(hp, 2, d.DWT2_F32, 3, ctypes.byref(n)) == 0 and n.value > 0
+    need = n.value
+    assert L.dwt2_workspace_bytes_batched(hp, 0, d.DWT2_F32, 3, ctypes.byref(n)) == -12
+    assert L.dwt2_workspace_bytes_batched(hp, 2, d.DWT2_F32, 9, ctypes.byref(n)) == -3
+
+    # every call below must fail its argument checks (the pointers are fake)
+    def fb(host=hp, dev_=0x50000000, count=2, dtype=d.DWT2_F32, wav=d.DWT2_CDF97, levels=3, boundary=0,
+           flags=0, ws=FAKE_WS, ws_n=need):
+        return L.dwt2_fwd_batched(host, ctypes.c_void_p(dev_), count, dtype, wav, levels, boundary, flags,
+                                  ctypes.c_void_p(ws), ws_n, None)
+    assert fb(host=None) == -1
+    assert fb(dev_=0) == -1
+    assert fb(ws=0) == -1
+    assert fb(count=0) == -12
+    assert fb(dtype=d.DWT2_I32) == -4
+    assert fb(wav=d.DWT2_CDF53_REV) == -5
+    assert fb(boundary=2) == -6
+    assert fb(levels=0) == -3
+    assert fb(ws_n=need - 1) == -8
+    stream_cfg = next(i for i in range(d.DWT2_NUM_KERNEL_CONFIGS)
+                      if d.dwt2_kernel_config(i)[1] == d.DWT2_ALGO_STREAM)
+    assert fb(flags=d.DWT2_FLAG_KERNEL(stream_cfg)) == -11   # not a batched configuration
+    assert fb(ws=FAKE_DST + 8) == -9
+    bad = (d.dwt2_image * 1)()
+    bad[0] = d.dwt2_image(FAKE_SRC, FAKE_SRC + 4, 64, 64, 64, 64)
+    assert fb(host=ctypes.cast(bad, ctypes.c_void_p), count=1) == -9
+    bad[0] = d.dwt2_image(FAKE_SRC, FAKE_DST, 1, 64, 64, 64)
+    assert fb(host=ctypes.cast(bad, ctypes.c_void_p), count=1) == -2
+
+
+def test_kernel_configs_listed():
+    for i in range(d.DWT2_NUM_KERNEL_CONFIGS):
+        st, algo, waves, rows, cc, cr = d.dwt2_kernel_config(i)
+        assert st == 0 and algo in (d.DWT2_ALGO_TILE, d.DWT2_ALGO_STREAM) and waves >= 1 and cr >= 1
+    assert d.dwt2_kernel_config(d.DWT2_NUM_KERNEL_CONFIGS)[0] == -11

@@ -1,4 +1,4 @@
-"""Batched forward transform: one persistent launch over many uneven images.
+"""Batched forward transform: one launch per level over many uneven images.
 
 Every image of the batch must equal the single-image dwt2_fwd on that image
 bit for bit (same kernel configuration: the same tile arithmetic), and a
@@ -40,7 +40,6 @@ def test_batched_equals_single(tdt, config):
     lv = min(5, min(lifting.max_levels(*s) for s in shapes))
     call = d.BatchedForward(xs, lv, config=config)
     outs = call.run()
-    assert call.error_word() == 0
     for x, y in zip(xs, outs):
         ref = d.fwd(x, "cdf97", lv, config=config)
         assert torch.equal(y, ref)
@@ -87,4 +86,4 @@ def test_batched_graph_replay():
         torch.cuda.synchronize()
         for y, e in zip(call.outs, eager):
             assert torch.equal(y, e), rep
-        assert call.error_word() == 0
+    
