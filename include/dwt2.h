@@ -180,10 +180,10 @@ int dwt2_workspace_bytes_batched(const dwt2_image* images, int count, dwt2_dtype
  * memory, read by the kernels; it must stay valid until the launches have
  * run).  The call performs no copies or allocations and can be captured in a
  * graph.  Float storage (F32, BF16, F16); flags: DWT2_FLAG_SPLIT and a tile
- * kernel configuration (indices 0 or 1 of dwt2_kernel_config).  No image's
+ * kernel configuration (any DWT2_ALGO_TILE index of dwt2_kernel_config).  No image's
  * src and dst may overlap each other or the workspace; distinct images must
  * not share a dst.  The sum over the images of one level's tiles must stay
- * below 2^31 (else DWT2_E_SHAPE).  Results equal dwt2_fwd on each image
+ * below 2^31 - 2^16 (else DWT2_E_SHAPE).  Results equal dwt2_fwd on each image
  * (bit-identical for the same configuration). */
 int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_images, int count,
                      dwt2_dtype dtype, dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,

@@ -130,7 +130,8 @@ void plan_grid(int cfg, dwt2::LevelParams* lp) {
     const int32_t nEr = (lp->h + 1) / 2, nEc = (lp->w + 1) / 2;
     if (c.algo == dwt2::kAlgoTile) {
         const int cy = dwt2::core_rows(c);
-        lp->tiles_x = (nEc + dwt2::kTileCoreBX - 1) / dwt2::kTileCoreBX;
+        const int cx = dwt2::core_cols(c);
+        lp->tiles_x = (nEc + cx - 1) / cx;
         lp->tiles_y = (nEr + cy - 1) / cy;
         lp->seg_rows = 0;
     } else {
@@ -174,9 +175,10 @@ int run_forward(const void* src, void* dst, int32_t h, int32_t w, int64_t sp, in
         lp.out_ll_pitch = last ? dp : ws_pitch((lp.w + 1) / 2);
         plan_grid(config_of(flags), &lp);
         const int32_t nEc = (lp.w + 1) / 2;
+        const int sv = dwt2::subband_vec(dwt2::kConfigs[config_of(flags)]);
         lp.vec = aligned(lp.in, 4 * es) && lp.in_pitch % 4 == 0 &&
-                 aligned(lp.out, 2 * es) && lp.out_pitch % 2 == 0 && nEc % 2 == 0 &&
-                 aligned(lp.out_ll, 2 * es) && lp.out_ll_pitch % 2 == 0;
+                 aligned(lp.out, sv * es) && lp.out_pitch % sv == 0 && nEc % sv == 0 &&
+                 aligned(lp.out_ll, sv * es) && lp.out_ll_pitch % sv == 0;
         const int rc = report(dwt2::launch_level(dwt2::kForward, to_wav(wavelet), to_dtype(dtype),
                                                  (flags & DWT2_FLAG_SPLIT) != 0, config_of(flags), lp, s));
         if (rc) return rc;
@@ -213,8 +215,9 @@ int run_backward(dwt2::Direction dir, const void* src, void* dst, int32_t h, int
         lp.out_pitch = l == 0 ? dp : ws_pitch(lp.w);
         plan_grid(config_of(flags), &lp);
         const int32_t nEc = (lp.w + 1) / 2;
-        lp.vec = aligned(lp.in, 2 * es) && lp.in_pitch % 2 == 0 && nEc % 2 == 0 &&
-                 aligned(lp.in_ll, 2 * es) && lp.in_ll_pitch % 2 == 0 &&
+        const int sv = dwt2::subband_vec(dwt2::kConfigs[config_of(flags)]);
+        lp.vec = aligned(lp.in, sv * es) && lp.in_pitch % sv == 0 && nEc % sv == 0 &&
+                 aligned(lp.in_ll, sv * es) && lp.in_ll_pitch % sv == 0 &&
                  aligned(lp.out, 4 * es) && lp.out_pitch % 4 == 0;
         const int rc = report(dwt2::launch_level(dir, to_wav(wavelet), to_dtype(dtype),
                                                  (flags & DWT2_FLAG_SPLIT) != 0, config_of(flags), lp, s));
@@ -286,7 +289,7 @@ int dwt2_kernel_config(int index, int* algorithm, int* waves, int* rows, int* co
     if (algorithm) *algorithm = c.algo;
     if (waves) *waves = c.waves;
     if (rows) *rows = c.rows;
-    if (core_cols) *core_cols = c.algo == dwt2::kAlgoTile ? dwt2::kTileCoreBX : dwt2::kStreamCoreBX;
+    if (core_cols) *core_cols = c.algo == dwt2::kAlgoTile ? dwt2::core_cols(c) : dwt2::kStreamCoreBX;
     if (core_rows) *core_rows = c.algo == dwt2::kAlgoTile ? dwt2::core_rows(c) : c.seg;
     return DWT2_OK;
 }
@@ -326,6 +329,7 @@ int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_ima
     if (!dwt2::batched_config_supported(cfg)) return DWT2_E_FLAGS;
     const size_t es = elem_size(dtype);
     const int core = dwt2::core_rows(dwt2::kConfigs[cfg]);
+    const int core_x = dwt2::core_cols(dwt2::kConfigs[cfg]);
     uint64_t tiles[32] = {0};
     for (int i = 0; i < count; ++i) {
         const dwt2_image& im = host_images[i];
@@ -336,11 +340,11 @@ int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_ima
         if (ranges_overlap(im.src, span_bytes(im.height, im.width, im.src_pitch, es), im.dst,
                            span_bytes(im.height, im.width, im.dst_pitch, es)))
             return DWT2_E_ALIAS;
-        for (int l = 0; l < levels; ++l) tiles[l] += dwt2::level_tile_count(im.height, im.width, l, core);
+        for (int l = 0; l < levels; ++l) tiles[l] += dwt2::level_tile_count(im.height, im.width, l, core_x, core);
     }
     uint32_t tiles_per_level[32];
     for (int l = 0; l < levels; ++l) {
-        if (tiles[l] > 0x7ffffff8ull) return DWT2_E_SHAPE;     // grid of one launch
+        if (tiles[l] > 0x7fff0000ull) return DWT2_E_SHAPE;     // grid of one launch
         tiles_per_level[l] = (uint32_t)tiles[l];
     }
     size_t need = 0;

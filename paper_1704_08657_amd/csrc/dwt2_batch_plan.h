@@ -46,17 +46,19 @@ __host__ __device__ inline void level_size(int32_t h, int32_t w, int l, int32_t*
     *wl = w;
 }
 
-// Tile grid of one level for the tile kernel with `core_rows` output block rows.
-__host__ __device__ inline void level_tiles(int32_t hl, int32_t wl, int core_rows, int32_t* tx, int32_t* ty) {
+// Tile grid of one level for the tile kernel with `core_cols` x `core_rows`
+// output blocks per tile.
+__host__ __device__ inline void level_tiles(int32_t hl, int32_t wl, int core_cols, int core_rows, int32_t* tx,
+                                            int32_t* ty) {
     const int32_t nEr = (hl + 1) / 2, nEc = (wl + 1) / 2;
-    *tx = (nEc + kTileCoreBX - 1) / kTileCoreBX;
+    *tx = (nEc + core_cols - 1) / core_cols;
     *ty = (nEr + core_rows - 1) / core_rows;
 }
 
-__host__ __device__ inline uint64_t level_tile_count(int32_t h, int32_t w, int l, int core_rows) {
+__host__ __device__ inline uint64_t level_tile_count(int32_t h, int32_t w, int l, int core_cols, int core_rows) {
     int32_t hl, wl, tx, ty;
     level_size(h, w, l, &hl, &wl);
-    level_tiles(hl, wl, core_rows, &tx, &ty);
+    level_tiles(hl, wl, core_cols, core_rows, &tx, &ty);
     return (uint64_t)tx * (uint64_t)ty;
 }
 

@@ -40,7 +40,8 @@ __device__ U block_scan(U v, U* sh, U* total) {
 }
 
 __global__ void __launch_bounds__(kPlanThreads)
-batch_plan_kernel(const dwt2_image* imgs, int count, int levels, int core_rows, int es, unsigned char* ws) {
+batch_plan_kernel(const dwt2_image* imgs, int count, int levels, int core_cols, int core_rows, int es,
+                  unsigned char* ws) {
     __shared__ uint32_t sh32[kPlanThreads];
     __shared__ uint64_t sh64[kPlanThreads];
     const int tid = threadIdx.x;
@@ -52,7 +53,7 @@ batch_plan_kernel(const dwt2_image* imgs, int count, int levels, int core_rows, 
         uint32_t carry = 0;
         for (int base = 0; base < count; base += kPlanThreads) {
             const int i = base + tid;
-            const uint32_t v = i < count ? (uint32_t)level_tile_count(imgs[i].height, imgs[i].width, l, core_rows) : 0u;
+            const uint32_t v = i < count ? (uint32_t)level_tile_count(imgs[i].height, imgs[i].width, l, core_cols, core_rows) : 0u;
             uint32_t tot;
             const uint32_t inc = block_scan(v, sh32, &tot);
             if (i < count) row[i] = carry + inc - v;
@@ -73,18 +74,18 @@ batch_plan_kernel(const dwt2_image* imgs, int count, int levels, int core_rows, 
 
 __device__ __forceinline__ bool is_aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-// Level l of every image.  The grid is a multiple of 8; work-groups are dealt
-// round-robin over the 8 XCDs, so each XCD is given a contiguous run of the
-// level's tiles (row-major within an image, images in order) and the halo
-// re-reads of neighbouring tiles hit its L2.
-template <typename T, bool SPLIT, int NW, int K>
+// Level l of every image.  The grid is a multiple of 8 chunks of kBatchChunk
+// tiles; work-groups are dealt round-robin over the 8 XCDs, so each XCD is
+// given runs of kBatchChunk consecutive tiles of the level (row-major within
+// an image, images in order) and the halo re-reads of neighbouring tiles hit
+// its L2.
+template <typename T, bool SPLIT, int NW, int K, int BPL>
 __global__ void __launch_bounds__(NW * kLanes)
 batched_level_kernel(const dwt2_image* imgs, int count, int levels, int l, unsigned char* ws) {
     using V = typename St<T>::V;
     constexpr int kCoreBY = NW * K - 2 * kHalo;
     constexpr size_t es = sizeof(T);
-    __shared__ Edge8<V> bufT[NW][kLanes];
-    __shared__ Edge8<V> bufS[NW][kLanes];
+    __shared__ TileLds<V, NW, BPL> lds;
     const int lane = threadIdx.x & (kLanes - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
     const BatchLayout L = batch_layout(count, levels);
@@ -92,8 +93,9 @@ batched_level_kernel(const dwt2_image* imgs, int count, int levels, int l, unsig
     const uint64_t* ll_off = reinterpret_cast<const uint64_t*>(ws + L.off_ll_off);
     unsigned char* ll_area = ws + L.off_ll;
 
-    const uint32_t per = gridDim.x >> 3;
-    const uint32_t t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    // XCD x takes chunks x, x + 8, ... of kBatchChunk consecutive tiles
+    const uint32_t j = blockIdx.x >> 3;
+    const uint32_t t = ((j / kBatchChunk) * 8 + (blockIdx.x & 7)) * kBatchChunk + j % kBatchChunk;
     if (t >= off[count]) return;                  // uniform over the work-group
     // image of tile t: off[] is strictly increasing (every image has a tile)
     int lo = 0, hi = count;
@@ -110,7 +112,7 @@ batched_level_kernel(const dwt2_image* imgs, int count, int levels, int l, unsig
     level_size(im.height, im.width, l, &hl, &wl);
     P.h = hl;
     P.w = wl;
-    level_tiles(hl, wl, kCoreBY, &P.tiles_x, &P.tiles_y);
+    level_tiles(hl, wl, Lay<BPL>::CORE_BX, kCoreBY, &P.tiles_x, &P.tiles_y);
     unsigned char* bufA = ll_area + ll_off[i];
     unsigned char* bufB = bufA + image_ll_b_offset(im.height, im.width, levels, es);
     if (l == 0) {
@@ -129,26 +131,27 @@ batched_level_kernel(const dwt2_image* imgs, int count, int levels, int l, unsig
         P.out_ll = l % 2 == 0 ? (void*)bufA : (void*)bufB;
         P.out_ll_pitch = ll_pitch((wl + 1) / 2);
     }
-    P.vec = is_aligned(P.in, 4 * es) && P.in_pitch % 4 == 0 && is_aligned(P.out, 2 * es) &&
-            P.out_pitch % 2 == 0 && ((wl + 1) / 2) % 2 == 0 && is_aligned(P.out_ll, 2 * es) &&
-            P.out_ll_pitch % 2 == 0;
+    P.vec = is_aligned(P.in, 4 * es) && P.in_pitch % 4 == 0 && is_aligned(P.out, BPL * es) &&
+            P.out_pitch % BPL == 0 && ((wl + 1) / 2) % BPL == 0 && is_aligned(P.out_ll, BPL * es) &&
+            P.out_ll_pitch % BPL == 0;
     const int ty = tt / P.tiles_x;
     const int tx = tt - ty * P.tiles_x;
-    tile_body<kForward, kCdf97, T, SPLIT, NW, K>(P, tx, ty, bufT, bufS, lane, wv);
+    tile_body<kForward, kCdf97, T, SPLIT, NW, K, BPL>(P, tx, ty, lds, lane, wv);
 }
 
-template <typename T, bool SPLIT, int NW, int K>
+template <typename T, bool SPLIT, int NW, int K, int BPL>
 hipError_t launch_batched_shape(const dwt2_image* dev_imgs, int count, int levels, void* ws,
                                 const uint32_t* tiles_per_level, hipStream_t s) {
     constexpr int kCoreBY = NW * K - 2 * kHalo;
     unsigned char* w = static_cast<unsigned char*>(ws);
-    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, dev_imgs, count, levels, kCoreBY,
-                       (int)sizeof(T), w);
+    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, dev_imgs, count, levels,
+                       Lay<BPL>::CORE_BX, kCoreBY, (int)sizeof(T), w);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     for (int l = 0; l < levels; ++l) {
-        const uint32_t grid = (tiles_per_level[l] + 7u) / 8u * 8u;
-        hipLaunchKernelGGL((batched_level_kernel<T, SPLIT, NW, K>), dim3(grid), dim3(NW * kLanes), 0, s, dev_imgs,
+        const uint32_t chunks = (tiles_per_level[l] + kBatchChunk - 1) / kBatchChunk;
+        const uint32_t grid = (chunks + 7u) / 8u * 8u * kBatchChunk;
+        hipLaunchKernelGGL((batched_level_kernel<T, SPLIT, NW, K, BPL>), dim3(grid), dim3(NW * kLanes), 0, s, dev_imgs,
                            count, levels, l, w);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -159,10 +162,18 @@ hipError_t launch_batched_shape(const dwt2_image* dev_imgs, int count, int level
 template <typename T, bool SPLIT>
 hipError_t launch_batched_cfg(int cfg, const dwt2_image* d, int count, int levels, void* ws, const uint32_t* tpl,
                               hipStream_t s) {
+    static_assert(kNumConfigs == 8, "dispatch table below lists every kernel configuration");
+#define DWT2_BCFG(i)                                                                               \
+    case i:                                                                                        \
+        if constexpr (kConfigs[i].algo == kAlgoTile)                                               \
+            return launch_batched_shape<T, SPLIT, kConfigs[i].waves, kConfigs[i].rows, kConfigs[i].bpl>( \
+                d, count, levels, ws, tpl, s);                                                     \
+        else                                                                                       \
+            return hipErrorInvalidValue;
     switch (cfg) {
-        case 0: return launch_batched_shape<T, SPLIT, kConfigs[0].waves, kConfigs[0].rows>(d, count, levels, ws, tpl, s);
-        case 1: return launch_batched_shape<T, SPLIT, kConfigs[1].waves, kConfigs[1].rows>(d, count, levels, ws, tpl, s);
+        DWT2_BCFG(0) DWT2_BCFG(1) DWT2_BCFG(2) DWT2_BCFG(3) DWT2_BCFG(4) DWT2_BCFG(5) DWT2_BCFG(6) DWT2_BCFG(7)
     }
+#undef DWT2_BCFG
     return hipErrorInvalidValue;
 }
 
@@ -176,12 +187,10 @@ hipError_t launch_batched_t(bool split, int cfg, const dwt2_image* d, int count,
 }  // namespace
 }  // namespace kern
 
-bool batched_config_supported(int cfg) { return cfg == 0 || cfg == 1; }
+bool batched_config_supported(int cfg) { return cfg >= 0 && cfg < kNumConfigs && kConfigs[cfg].algo == kAlgoTile; }
 
 hipError_t launch_fwd_batched(Dtype dt, bool split, int cfg, const dwt2_image* dev_imgs, int count, int levels,
                               void* ws, const uint32_t* tiles_per_level, hipStream_t s) {
-    static_assert(kConfigs[0].algo == kAlgoTile && kConfigs[1].algo == kAlgoTile,
-                  "batched kernels are instantiated for tile configurations 0 and 1");
     switch (dt) {
         case kF32: return kern::launch_batched_t<float>(split, cfg, dev_imgs, count, levels, ws, tiles_per_level, s);
         case kBF16:

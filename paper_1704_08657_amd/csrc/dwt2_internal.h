@@ -14,18 +14,19 @@ enum Wavelet : int { kCdf97 = 0, kCdf53 = 1 };
 enum Dtype : int { kF32 = 0, kBF16 = 1, kF16 = 2, kI32 = 3 };
 
 // Geometry shared by host planning and the kernels, in blocks of 2x2 pixels.
-// A tile (kAlgoTile) has 128 output columns and waves * rows - 2 * kHalo
-// output rows; a halo of kHalo blocks on every side is recomputed and
-// discarded.  A stream strip (kAlgoStream) has 124 output columns.
+// A tile (kAlgoTile) has 64 * bpl output columns (bpl blocks per lane) and
+// waves * rows - 2 * kHalo output rows; a halo of kHalo blocks on every side
+// is recomputed and discarded.  A stream strip (kAlgoStream) has 124 output
+// columns.
 constexpr int kLanes = 64;
 constexpr int kHalo = 2;
-constexpr int kTileCoreBX = 2 * kLanes;                   // tile kernel: 128 output columns
 constexpr int kStreamCoreBX = 2 * kLanes - 2 * kHalo;     // stream kernel: 124 (halo in the edge lanes)
 
 // Kernel configurations.
 //  kAlgoTile:   one work-group = `waves` wave64s stacked vertically, one tile
-//               of 128 x (waves * rows) blocks held in VGPRs (`rows` block rows
-//               per lane), one barrier per fused step.
+//               of (64 * bpl) x (waves * rows) blocks held in VGPRs (`rows`
+//               block rows and `bpl` block columns per lane, plus a halo
+//               pair), one barrier per fused step.
 //  kAlgoStream: every wave64 walks down its own column strip of 128 blocks,
 //               `rows` block rows of loads in flight ahead of the computation;
 //               `waves` strips per work-group; `seg` block rows per segment.
@@ -35,15 +36,24 @@ struct KernelConfig {
     int waves;
     int rows;
     int seg;
+    int bpl;    // kAlgoTile: block columns per lane (2 or 4)
 };
 constexpr KernelConfig kConfigs[] = {
-    {kAlgoTile, 4, 4, 0},    {kAlgoTile, 8, 4, 0},    {kAlgoTile, 6, 4, 0},
-    {kAlgoTile, 4, 6, 0},    {kAlgoTile, 8, 2, 0},    {kAlgoStream, 4, 8, 64},
-    {kAlgoStream, 1, 8, 64}, {kAlgoStream, 4, 8, 32}};
+    {kAlgoTile, 4, 4, 0, 2},    {kAlgoTile, 8, 4, 0, 2},    {kAlgoTile, 4, 4, 0, 4},
+    {kAlgoTile, 4, 6, 0, 2},    {kAlgoTile, 8, 2, 0, 4},    {kAlgoStream, 4, 8, 64, 2},
+    {kAlgoStream, 1, 8, 64, 2}, {kAlgoStream, 4, 8, 32, 2}};
 constexpr int kNumConfigs = 8;
 constexpr int kDefaultConfig = 0;
-// output block rows of one tile (kAlgoTile)
+// Tile kernels deal work over the 8 XCDs in chunks of kRemapRows tile rows
+// (a level) or kBatchChunk tiles (a batched launch); the grid is a multiple
+// of 8 chunks.
+constexpr int kRemapRows = 2;
+constexpr int kBatchChunk = 64;
+// output block rows / columns of one tile (kAlgoTile)
 constexpr int core_rows(KernelConfig c) { return c.waves * c.rows - 2 * kHalo; }
+constexpr int core_cols(KernelConfig c) { return kLanes * c.bpl; }
+// samples per vector access of a subband row (alignment the `vec` path needs)
+constexpr int subband_vec(KernelConfig c) { return c.algo == kAlgoTile ? c.bpl : 2; }
 
 // One level of a transform.  Forward: `in` is the h x w image of this level,
 // `out` the origin of this level's region of the Mallat pyramid (details are
@@ -71,8 +81,8 @@ struct LevelParams {
 hipError_t launch_level(Direction dir, Wavelet wav, Dtype dt, bool split, int cfg,
                         const LevelParams& p, hipStream_t stream);
 
-// Batched forward CDF 9/7 (planner + one launch per level) for tile
-// configurations `cfg` with batched_config_supported(cfg).
+// Batched forward CDF 9/7 (planner + one launch per level) for the tile
+// kernel configurations (batched_config_supported).
 // `tiles_per_level[l]` (host array of `levels` entries) is the number of
 // tiles of level l summed over the images: it sizes that level's grid.
 bool batched_config_supported(int cfg);

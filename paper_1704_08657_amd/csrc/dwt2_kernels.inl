@@ -13,26 +13,27 @@
 // `split` variant.
 //
 // Mapping to gfx950 (not the paper's OpenCL or shader design):
-//   * one work-group = NW wave64s = one tile of 128 x (NW * K) blocks
-//     (e.g. 256 x 128 pixels for NW = K = 8) with a 2-block halo recomputed
-//     on every side;
-//   * each lane owns two horizontally adjacent blocks ("L" and "R") for K
-//     consecutive block rows, all in VGPRs: K rows x 2 blocks x 4 components;
+//   * one work-group = NW wave64s = one tile of (64 * BPL) x (NW * K) blocks
+//     (e.g. 256 x 32 pixels for BPL = 2, NW = K = 4) with a 2-block halo
+//     recomputed on every side;
+//   * each lane owns BPL horizontally adjacent blocks (2 or 4) for K
+//     consecutive block rows, all in VGPRs, plus a halo pair used by the
+//     first and last lane only;
 //   * a step reads neighbours at +1 (predict-shaped: right / down) or at -1
 //     (update-shaped: left / up).  Horizontal neighbours come from the
 //     adjacent lane through DPP wave shifts, vertical ones from the lane's own
 //     registers, except at the boundary between two waves, where the edge row
 //     is published to LDS before the step's single s_barrier (two LDS buffers,
 //     one for each step shape, so one barrier per step suffices);
-//   * loads are 4-pixel vectors per image row, stores are 2-block vectors per
-//     subband row, both coalesced across the wave;
+//   * loads are 4-pixel vectors per image row, stores are BPL-sample vectors
+//     per subband row, both coalesced across the wave;
 //   * tiles touching the image border take a path that clamps neighbour
 //     indices into each component's extent (whole-point symmetric extension)
 //     or, for the adjoint, applies the transposed border weights; interior
 //     tiles take a branch-free path;
-//   * the tile index is remapped so that consecutive tiles of the image land
-//     on the same XCD (work-groups are dealt round-robin over the 8 XCDs), so
-//     the halo re-reads of neighbouring tiles hit that XCD's L2.
+//   * the tile index is remapped so that each XCD (work-groups are dealt
+//     round-robin over the 8 XCDs) takes whole rows of tiles, so the halo
+//     re-reads of neighbouring tiles hit that XCD's L2.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -285,196 +286,205 @@ __device__ __forceinline__ void minus_block(V& x0, V& x1, V& x2, V& x3,
 }
 
 // ---------------------------------------------------------------------------
-// Tile kernel.  A lane holds, for each of its K block rows, four blocks:
-// L and R = tile columns 2*lane and 2*lane+1 (the tile's 128 output
-// columns), and a halo pair E0, E1 that only lanes 0 and 63 use: tile columns
-// -2, -1 (lane 0) and 128, 129 (lane 63).  The output columns of a tile are
-// then aligned to 512-byte subband rows, so every store covers whole cache
-// lines; the halo pair costs extra arithmetic, which is hidden behind memory.
-// a[r][0..3] = L.x0..x3, [4..7] = R, [8..11] = E0, [12..15] = E1.
+// Tile kernel.  A lane holds, for each of its K block rows, BPL + 2 blocks:
+// B0 .. B(BPL-1) = tile columns BPL*lane .. BPL*lane + BPL - 1 (the tile's
+// 64 * BPL output columns), and a halo pair E0, E1 that only lanes 0 and 63
+// use: tile columns -2, -1 (lane 0) and 64*BPL, 64*BPL + 1 (lane 63).  The
+// output columns of a tile are then aligned to whole subband rows of 64 * BPL
+// samples, so every store covers whole cache lines; the halo pair costs
+// extra arithmetic (2 of the lane's BPL + 2 blocks), which is hidden behind
+// memory.  a[r][4 b + k] = component x_k of block b (b = BPL: E0, BPL+1: E1).
 // ---------------------------------------------------------------------------
-constexpr int kL = 0, kR = 4, kE0 = 8, kE1 = 12;
-constexpr int kBX = 16;                           // values per register row
+template <int BPL> struct Lay {
+    static_assert(BPL == 2 || BPL == 4, "2 or 4 blocks per lane");
+    static constexpr int NB = BPL + 2;            // blocks per lane and row
+    static constexpr int BX = 4 * NB;             // values per register row
+    static constexpr int E0 = 4 * BPL, E1 = 4 * BPL + 4;
+    static constexpr int LAST = 4 * (BPL - 1);    // last core block
+    static constexpr int NG = NB / 2;             // Vec4 groups of one edge row (2 values per block)
+    static constexpr int CORE_BX = kLanes * BPL;  // output block columns of a tile
+};
 
 struct LaneRole {
     bool l0, l63;
 };
 
-// Operands of a predict-shaped step for the four blocks of one row, all taken
+// Operands of a predict-shaped step for the blocks of one row, all taken
 // before the step: right neighbour (x0R, x2R), lower (x0D, x1D), lower-right (x0DR).
-template <typename V> struct PlusOps { V x0R[4], x2R[4], x0D[4], x1D[4], x0DR[4]; };
+template <typename V, int NB> struct PlusOps { V x0R[NB], x2R[NB], x0D[NB], x1D[NB], x0DR[NB]; };
 // Operands of an update-shaped step: left (x1l, x3l), upper (x2u, x3u), upper-left (x3ul).
-template <typename V> struct MinusOps { V x1l[4], x3l[4], x2u[4], x3u[4], x3ul[4]; };
+template <typename V, int NB> struct MinusOps { V x1l[NB], x3l[NB], x2u[NB], x3u[NB], x3ul[NB]; };
 
-// cur: the row; dn: the row below (x0, x1 used); dnRL0: the right lane's L.x0
-// of the row below (E0.x0 in lane 63).  The right neighbour of R is the next
-// lane's L, or E0 in lane 63; the right neighbour of E1 is L (block -1 -> 0 in
-// lane 0; in lane 63, block 129 is outermost halo and any value will do).
-template <typename V>
-__device__ __forceinline__ void gather_plus(const V (&cur)[kBX], const V (&dn)[kBX], V dnRL0, LaneRole lr,
-                                            PlusOps<V>& o) {
-    (void)lr;
-    o.x0R[0] = cur[kR + 0]; o.x2R[0] = cur[kR + 2];                          // L -> R
-    o.x0D[0] = dn[kL + 0]; o.x1D[0] = dn[kL + 1]; o.x0DR[0] = dn[kR + 0];
-    o.x0R[1] = from_right_or(cur[kE0 + 0], cur[kL + 0]);                     // R -> next lane's L
-    o.x2R[1] = from_right_or(cur[kE0 + 2], cur[kL + 2]);
-    o.x0D[1] = dn[kR + 0]; o.x1D[1] = dn[kR + 1]; o.x0DR[1] = dnRL0;
-    o.x0R[2] = cur[kE1 + 0]; o.x2R[2] = cur[kE1 + 2];                        // E0 -> E1
-    o.x0D[2] = dn[kE0 + 0]; o.x1D[2] = dn[kE0 + 1]; o.x0DR[2] = dn[kE1 + 0];
-    o.x0R[3] = cur[kL + 0]; o.x2R[3] = cur[kL + 2];                          // E1 -> L
-    o.x0D[3] = dn[kE1 + 0]; o.x1D[3] = dn[kE1 + 1]; o.x0DR[3] = dn[kL + 0];
+// cur: the row; dn: the row below (x0, x1 used); dnRB0: the right lane's
+// B0.x0 of the row below (E0.x0 in lane 63).  The right neighbour of the
+// last core block is the next lane's B0, or E0 in lane 63; the right
+// neighbour of E1 is B0 (block -1 -> 0 in lane 0; in lane 63, block
+// 64*BPL + 1 is outermost halo and any value will do).
+template <int BPL, typename V>
+__device__ __forceinline__ void gather_plus(const V (&cur)[Lay<BPL>::BX], const V (&dn)[Lay<BPL>::BX], V dnRB0,
+                                            PlusOps<V, Lay<BPL>::NB>& o) {
+    using L = Lay<BPL>;
+#pragma unroll
+    for (int b = 0; b + 1 < BPL; ++b) {                                      // B(b) -> B(b+1)
+        o.x0R[b] = cur[4 * b + 4]; o.x2R[b] = cur[4 * b + 6];
+        o.x0D[b] = dn[4 * b]; o.x1D[b] = dn[4 * b + 1]; o.x0DR[b] = dn[4 * b + 4];
+    }
+    constexpr int b = BPL - 1;                                               // -> next lane's B0
+    o.x0R[b] = from_right_or(cur[L::E0 + 0], cur[0]);
+    o.x2R[b] = from_right_or(cur[L::E0 + 2], cur[2]);
+    o.x0D[b] = dn[L::LAST]; o.x1D[b] = dn[L::LAST + 1]; o.x0DR[b] = dnRB0;
+    o.x0R[BPL] = cur[L::E1 + 0]; o.x2R[BPL] = cur[L::E1 + 2];                // E0 -> E1
+    o.x0D[BPL] = dn[L::E0]; o.x1D[BPL] = dn[L::E0 + 1]; o.x0DR[BPL] = dn[L::E1];
+    o.x0R[BPL + 1] = cur[0]; o.x2R[BPL + 1] = cur[2];                        // E1 -> B0
+    o.x0D[BPL + 1] = dn[L::E1]; o.x1D[BPL + 1] = dn[L::E1 + 1]; o.x0DR[BPL + 1] = dn[0];
 }
 
-// cur: the row; up: the row above (x2, x3 used); upLR3: the left lane's R.x3
-// of the row above (E1.x3 in lane 0).  The left neighbour of L is the
-// previous lane's R, or E1 in lane 0; the left neighbour of E0 is R (block
-// 128 -> 127 in lane 63; in lane 0, block -2 is outermost halo).
-template <typename V>
-__device__ __forceinline__ void gather_minus(const V (&cur)[kBX], const V (&up)[kBX], V upLR3, LaneRole lr,
-                                             MinusOps<V>& o) {
-    (void)lr;
-    o.x1l[0] = from_left_or(cur[kE1 + 1], cur[kR + 1]);                      // L <- previous lane's R
-    o.x3l[0] = from_left_or(cur[kE1 + 3], cur[kR + 3]);
-    o.x2u[0] = up[kL + 2]; o.x3u[0] = up[kL + 3]; o.x3ul[0] = upLR3;
-    o.x1l[1] = cur[kL + 1]; o.x3l[1] = cur[kL + 3];                          // R <- L
-    o.x2u[1] = up[kR + 2]; o.x3u[1] = up[kR + 3]; o.x3ul[1] = up[kL + 3];
-    o.x1l[2] = cur[kR + 1]; o.x3l[2] = cur[kR + 3];                          // E0 <- R
-    o.x2u[2] = up[kE0 + 2]; o.x3u[2] = up[kE0 + 3]; o.x3ul[2] = up[kR + 3];
-    o.x1l[3] = cur[kE0 + 1]; o.x3l[3] = cur[kE0 + 3];                        // E1 <- E0
-    o.x2u[3] = up[kE1 + 2]; o.x3u[3] = up[kE1 + 3]; o.x3ul[3] = up[kE0 + 3];
+// cur: the row; up: the row above (x2, x3 used); upLB3: the left lane's
+// last core block's x3 of the row above (E1.x3 in lane 0).  The left
+// neighbour of B0 is the previous lane's last core block, or E1 in lane 0;
+// the left neighbour of E0 is the last core block (block 64*BPL -> 64*BPL - 1
+// in lane 63; in lane 0, block -2 is outermost halo).
+template <int BPL, typename V>
+__device__ __forceinline__ void gather_minus(const V (&cur)[Lay<BPL>::BX], const V (&up)[Lay<BPL>::BX], V upLB3,
+                                             MinusOps<V, Lay<BPL>::NB>& o) {
+    using L = Lay<BPL>;
+    o.x1l[0] = from_left_or(cur[L::E1 + 1], cur[L::LAST + 1]);              // B0 <- previous lane
+    o.x3l[0] = from_left_or(cur[L::E1 + 3], cur[L::LAST + 3]);
+    o.x2u[0] = up[2]; o.x3u[0] = up[3]; o.x3ul[0] = upLB3;
+#pragma unroll
+    for (int b = 1; b < BPL; ++b) {                                          // B(b) <- B(b-1)
+        o.x1l[b] = cur[4 * b - 3]; o.x3l[b] = cur[4 * b - 1];
+        o.x2u[b] = up[4 * b + 2]; o.x3u[b] = up[4 * b + 3]; o.x3ul[b] = up[4 * b - 1];
+    }
+    o.x1l[BPL] = cur[L::LAST + 1]; o.x3l[BPL] = cur[L::LAST + 3];            // E0 <- last core block
+    o.x2u[BPL] = up[L::E0 + 2]; o.x3u[BPL] = up[L::E0 + 3]; o.x3ul[BPL] = up[L::LAST + 3];
+    o.x1l[BPL + 1] = cur[L::E0 + 1]; o.x3l[BPL + 1] = cur[L::E0 + 3];        // E1 <- E0
+    o.x2u[BPL + 1] = up[L::E1 + 2]; o.x3u[BPL + 1] = up[L::E1 + 3]; o.x3ul[BPL + 1] = up[L::E0 + 3];
 }
 
 // EMASK selects the halo blocks a step must update (bit 0: E0, bit 1: E1).
-// Going backwards from the 128 output columns, a predict-shaped step widens
-// the columns the previous stage must provide by one to the right, an
+// Going backwards from the tile's output columns, a predict-shaped step
+// widens the columns the previous stage must provide by one to the right, an
 // update-shaped step by one to the left; a halo block is updated only at the
-// steps whose stage is needed at its column (-2, -1 in lane 0; 128, 129 in
-// lane 63).  Skipped halo values are never read by a needed value.
-template <int KIND, int EMASK, bool EX, bool EY, typename V>
-__device__ __forceinline__ void apply_plus(V (&cur)[kBX], const PlusOps<V>& o, const int (&gc)[4], int gr,
-                                           const Geo& g, float c) {
+// steps whose stage is needed at its column (-2, -1 in lane 0; 64*BPL,
+// 64*BPL + 1 in lane 63).  Skipped halo values are never read by a needed value.
+template <int KIND, int EMASK, bool EX, bool EY, int BPL, typename V>
+__device__ __forceinline__ void apply_plus(V (&cur)[Lay<BPL>::BX], const PlusOps<V, Lay<BPL>::NB>& o,
+                                           const int (&gc)[Lay<BPL>::NB], int gr, const Geo& g, float c) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-        if (b < 2 || (EMASK >> (b - 2)) & 1)
+    for (int b = 0; b < Lay<BPL>::NB; ++b)
+        if (b < BPL || (EMASK >> (b - BPL)) & 1)
             plus_block<KIND, EX, EY>(cur[4 * b], cur[4 * b + 1], cur[4 * b + 2], cur[4 * b + 3], o.x0R[b],
                                      o.x2R[b], o.x0D[b], o.x1D[b], o.x0DR[b], gc[b], gr, g, c);
 }
 
-template <int KIND, int EMASK, bool EX, bool EY, typename V>
-__device__ __forceinline__ void apply_minus(V (&cur)[kBX], const MinusOps<V>& o, const int (&gc)[4], int gr,
-                                            const Geo& g, float c) {
+template <int KIND, int EMASK, bool EX, bool EY, int BPL, typename V>
+__device__ __forceinline__ void apply_minus(V (&cur)[Lay<BPL>::BX], const MinusOps<V, Lay<BPL>::NB>& o,
+                                            const int (&gc)[Lay<BPL>::NB], int gr, const Geo& g, float c) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-        if (b < 2 || (EMASK >> (b - 2)) & 1)
+    for (int b = 0; b < Lay<BPL>::NB; ++b)
+        if (b < BPL || (EMASK >> (b - BPL)) & 1)
             minus_block<KIND, EX, EY>(cur[4 * b], cur[4 * b + 1], cur[4 * b + 2], cur[4 * b + 3], o.x1l[b],
                                       o.x3l[b], o.x2u[b], o.x3u[b], o.x3ul[b], gc[b], gr, g, c);
 }
 
-// Edge rows exchanged between the waves of a tile: x0, x1 of the top row (read
-// by predict-shaped steps of the wave above) and x2, x3 of the bottom row (read
-// by update-shaped steps of the wave below), for the four blocks of a lane.
-template <typename V> struct Edge8 { Vec4<V> m, e; };
-
-template <int K, typename V>
-__device__ __forceinline__ void publish_top(V (&a)[K][kBX], Edge8<V> (*buf)[kLanes], int lane, int wv) {
-    buf[wv][lane].m = Vec4<V>{a[0][kL + 0], a[0][kL + 1], a[0][kR + 0], a[0][kR + 1]};
-    buf[wv][lane].e = Vec4<V>{a[0][kE0 + 0], a[0][kE0 + 1], a[0][kE1 + 0], a[0][kE1 + 1]};
+// Edge rows exchanged between the waves of a tile: x0, x1 of the top row
+// (read by predict-shaped steps of the wave above) and x2, x3 of the bottom
+// row (read by update-shaped steps of the wave below), for every block of a
+// lane, as NG groups of four values.  Group-major layout buf[wave][group][lane]:
+// the 16-byte accesses of a wave are contiguous, free of bank conflicts.
+template <int BPL, typename V>
+__device__ __forceinline__ void publish_row(const V (&row)[Lay<BPL>::BX], int k0, Vec4<V> (*buf)[kLanes],
+                                            int lane) {
+#pragma unroll
+    for (int q = 0; q < Lay<BPL>::NG; ++q)
+        buf[q][lane] = Vec4<V>{row[8 * q + k0], row[8 * q + k0 + 1], row[8 * q + 4 + k0], row[8 * q + 4 + k0 + 1]};
 }
-template <int K, typename V>
-__device__ __forceinline__ void publish_bottom(V (&a)[K][kBX], Edge8<V> (*buf)[kLanes], int lane, int wv) {
-    buf[wv][lane].m = Vec4<V>{a[K - 1][kL + 2], a[K - 1][kL + 3], a[K - 1][kR + 2], a[K - 1][kR + 3]};
-    buf[wv][lane].e = Vec4<V>{a[K - 1][kE0 + 2], a[K - 1][kE0 + 3], a[K - 1][kE1 + 2], a[K - 1][kE1 + 3]};
+template <int BPL, typename V>
+__device__ __forceinline__ void fetch_row(V (&row)[Lay<BPL>::BX], int k0, Vec4<V> (*buf)[kLanes], int lane) {
+#pragma unroll
+    for (int q = 0; q < Lay<BPL>::NG; ++q) {
+        const Vec4<V> v = buf[q][lane];
+        row[8 * q + k0] = v.a; row[8 * q + k0 + 1] = v.b;
+        row[8 * q + 4 + k0] = v.c; row[8 * q + 4 + k0 + 1] = v.d;
+    }
 }
 
 // Predict-shaped step over the tile: rows top to bottom, so row r+1 is still
 // unmodified when row r reads it.
-template <int KIND, int EMASK, bool EDGE, int NW, int K, typename V>
-__device__ __forceinline__ void plus_step(V (&a)[K][kBX], Edge8<V> (*buf)[kLanes], int lane, int wv,
-                                          const Geo& g, const int (&gc)[4], LaneRole lr, float c) {
+template <int KIND, int EMASK, bool EDGE, int NW, int BPL, int K, typename V>
+__device__ __forceinline__ void plus_step(V (&a)[K][Lay<BPL>::BX], Vec4<V> (*buf)[Lay<BPL>::NG][kLanes], int lane,
+                                          int wv, const Geo& g, const int (&gc)[Lay<BPL>::NB], float c) {
+    using L = Lay<BPL>;
 #pragma unroll
     for (int r = 0; r < K; ++r) {
-        PlusOps<V> o;
+        PlusOps<V, L::NB> o;
         if (r + 1 < K) {
-            gather_plus(a[r], a[r + 1], from_right_or(a[r + 1][kE0 + 0], a[r + 1][kL + 0]), lr, o);
-        } else {
-            V dn[kBX];
-            V rl0;
-            if (wv + 1 < NW) {
-                const Edge8<V> q = buf[wv + 1][lane];
-                dn[kL + 0] = q.m.a; dn[kL + 1] = q.m.b; dn[kR + 0] = q.m.c; dn[kR + 1] = q.m.d;
-                dn[kE0 + 0] = q.e.a; dn[kE0 + 1] = q.e.b; dn[kE1 + 0] = q.e.c; dn[kE1 + 1] = q.e.d;
-                rl0 = lane < kLanes - 1 ? buf[wv + 1][lane + 1].m.a : q.e.a;
-            } else {                              // below the tile: halo, any finite value
-#pragma unroll
-                for (int q = 0; q < kBX; ++q) dn[q] = a[r][q];
-                rl0 = from_right_or(a[r][kE0 + 0], a[r][kL + 0]);
-            }
-            gather_plus(a[r], dn, rl0, lr, o);
+            gather_plus<BPL>(a[r], a[r + 1], from_right_or(a[r + 1][L::E0], a[r + 1][0]), o);
+        } else if (wv + 1 < NW) {
+            V dn[L::BX];
+            fetch_row<BPL>(dn, 0, buf[wv + 1], lane);
+            gather_plus<BPL>(a[r], dn, from_right_or(dn[L::E0], dn[0]), o);
+        } else {                                  // below the tile: halo, any finite value
+            gather_plus<BPL>(a[r], a[r], from_right_or(a[r][L::E0], a[r][0]), o);
         }
-        apply_plus<KIND, EMASK, EDGE, EDGE>(a[r], o, gc, g.gr0 + r, g, c);
+        apply_plus<KIND, EMASK, EDGE, EDGE, BPL>(a[r], o, gc, g.gr0 + r, g, c);
     }
 }
 
 // Update-shaped step over the tile: rows bottom to top.
-template <int KIND, int EMASK, bool EDGE, int NW, int K, typename V>
-__device__ __forceinline__ void minus_step(V (&a)[K][kBX], Edge8<V> (*buf)[kLanes], int lane, int wv,
-                                           const Geo& g, const int (&gc)[4], LaneRole lr, float c) {
+template <int KIND, int EMASK, bool EDGE, int NW, int BPL, int K, typename V>
+__device__ __forceinline__ void minus_step(V (&a)[K][Lay<BPL>::BX], Vec4<V> (*buf)[Lay<BPL>::NG][kLanes], int lane,
+                                           int wv, const Geo& g, const int (&gc)[Lay<BPL>::NB], float c) {
+    using L = Lay<BPL>;
 #pragma unroll
     for (int r = K - 1; r >= 0; --r) {
-        MinusOps<V> o;
+        MinusOps<V, L::NB> o;
         if (r > 0) {
-            gather_minus(a[r], a[r - 1], from_left_or(a[r - 1][kE1 + 3], a[r - 1][kR + 3]), lr, o);
-        } else {
-            V up[kBX];
-            V lr3;
-            if (wv > 0) {
-                const Edge8<V> q = buf[wv - 1][lane];
-                up[kL + 2] = q.m.a; up[kL + 3] = q.m.b; up[kR + 2] = q.m.c; up[kR + 3] = q.m.d;
-                up[kE0 + 2] = q.e.a; up[kE0 + 3] = q.e.b; up[kE1 + 2] = q.e.c; up[kE1 + 3] = q.e.d;
-                lr3 = lane > 0 ? buf[wv - 1][lane - 1].m.d : q.e.d;
-            } else {                              // above the tile: halo
-#pragma unroll
-                for (int q = 0; q < kBX; ++q) up[q] = a[r][q];
-                lr3 = from_left_or(a[r][kE1 + 3], a[r][kR + 3]);
-            }
-            gather_minus(a[r], up, lr3, lr, o);
+            gather_minus<BPL>(a[r], a[r - 1], from_left_or(a[r - 1][L::E1 + 3], a[r - 1][L::LAST + 3]), o);
+        } else if (wv > 0) {
+            V up[L::BX];
+            fetch_row<BPL>(up, 2, buf[wv - 1], lane);
+            gather_minus<BPL>(a[r], up, from_left_or(up[L::E1 + 3], up[L::LAST + 3]), o);
+        } else {                                  // above the tile: halo
+            gather_minus<BPL>(a[r], a[r], from_left_or(a[r][L::E1 + 3], a[r][L::LAST + 3]), o);
         }
-        apply_minus<KIND, EMASK, EDGE, EDGE>(a[r], o, gc, g.gr0 + r, g, c);
+        apply_minus<KIND, EMASK, EDGE, EDGE, BPL>(a[r], o, gc, g.gr0 + r, g, c);
     }
 }
 
 // Constant parts of the split (no neighbour access): separable lifting with
 // P0 = c (horizontal, then vertical) and with U0 = c, for every block.
-template <int K, typename V>
-__device__ __forceinline__ void local_predict(V (&a)[K][kBX], float c) {
+template <int K, int BX, typename V>
+__device__ __forceinline__ void local_predict(V (&a)[K][BX], float c) {
 #pragma unroll
     for (int r = 0; r < K; ++r)
 #pragma unroll
-        for (int b = 0; b < kBX; b += 4) {
+        for (int b = 0; b < BX; b += 4) {
             a[r][b + 1] = fmaf(c, a[r][b + 0], a[r][b + 1]);
             a[r][b + 3] = fmaf(c, a[r][b + 2], a[r][b + 3]);
             a[r][b + 2] = fmaf(c, a[r][b + 0], a[r][b + 2]);
             a[r][b + 3] = fmaf(c, a[r][b + 1], a[r][b + 3]);
         }
 }
-template <int K, typename V>
-__device__ __forceinline__ void local_update(V (&a)[K][kBX], float c) {
+template <int K, int BX, typename V>
+__device__ __forceinline__ void local_update(V (&a)[K][BX], float c) {
 #pragma unroll
     for (int r = 0; r < K; ++r)
 #pragma unroll
-        for (int b = 0; b < kBX; b += 4) {
+        for (int b = 0; b < BX; b += 4) {
             a[r][b + 0] = fmaf(c, a[r][b + 1], a[r][b + 0]);
             a[r][b + 2] = fmaf(c, a[r][b + 3], a[r][b + 2]);
             a[r][b + 0] = fmaf(c, a[r][b + 2], a[r][b + 0]);
             a[r][b + 1] = fmaf(c, a[r][b + 3], a[r][b + 1]);
         }
 }
-template <int K, typename V>
-__device__ __forceinline__ void scale(V (&a)[K][kBX], float s0, float s3) {
+template <int K, int BX, typename V>
+__device__ __forceinline__ void scale(V (&a)[K][BX], float s0, float s3) {
 #pragma unroll
     for (int r = 0; r < K; ++r)
 #pragma unroll
-        for (int b = 0; b < kBX; b += 4) {
+        for (int b = 0; b < BX; b += 4) {
             a[r][b + 0] *= s0;
             a[r][b + 3] *= s3;
         }
@@ -482,13 +492,14 @@ __device__ __forceinline__ void scale(V (&a)[K][kBX], float s0, float s3) {
 
 // The step program of one scale.  Each "sync" is the single barrier of one
 // fused step; the LDS edge row it guards is published just before it.
-template <int DIR, int WAV, bool EDGE, bool SPLIT, int NW, int K, typename V>
-__device__ __forceinline__ void run(V (&a)[K][kBX], Edge8<V> (*bT)[kLanes], Edge8<V> (*bS)[kLanes],
-                                    int lane, int wv, const Geo& g, const int (&gc)[4], LaneRole lr) {
-#define DWT2_PLUS(KIND_, M_, c_) publish_top(a, bT, lane, wv); __syncthreads(); \
-    plus_step<KIND_, M_, EDGE, NW>(a, bT, lane, wv, g, gc, lr, (c_));
-#define DWT2_MINUS(KIND_, M_, c_) publish_bottom(a, bS, lane, wv); __syncthreads(); \
-    minus_step<KIND_, M_, EDGE, NW>(a, bS, lane, wv, g, gc, lr, (c_));
+template <int DIR, int WAV, bool EDGE, bool SPLIT, int NW, int BPL, int K, typename V>
+__device__ __forceinline__ void run(V (&a)[K][Lay<BPL>::BX], Vec4<V> (*bT)[Lay<BPL>::NG][kLanes],
+                                    Vec4<V> (*bS)[Lay<BPL>::NG][kLanes], int lane, int wv, const Geo& g,
+                                    const int (&gc)[Lay<BPL>::NB]) {
+#define DWT2_PLUS(KIND_, M_, c_) publish_row<BPL>(a[0], 0, bT[wv], lane); __syncthreads(); \
+    plus_step<KIND_, M_, EDGE, NW, BPL>(a, bT, lane, wv, g, gc, (c_));
+#define DWT2_MINUS(KIND_, M_, c_) publish_row<BPL>(a[K - 1], 2, bS[wv], lane); __syncthreads(); \
+    minus_step<KIND_, M_, EDGE, NW, BPL>(a, bS, lane, wv, g, gc, (c_));
     // halo masks (E0 = 1, E1 = 2) per step, from the column ranges each stage
     // must cover: predict/update/predict/update -> 3, 3, 2, 0;
     // update/predict/update/predict -> 3, 3, 1, 0; predict/update -> 2, 0;
@@ -649,11 +660,54 @@ __device__ __forceinline__ void store2(T* rowp, int gc, int ncols, bool vec,
     }
 }
 
-// Load the tile (halo included) into registers.
-template <int DIR, typename T, bool EDGE, int K>
-__device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][kBX], const LevelParams& P, const Geo& g,
-                                          int gcE0, LaneRole lr) {
+// N consecutive samples (blocks gc .. gc+N-1; gc a multiple of N) of one
+// subband row with `ncols` columns; outside the row (or !row_ok) read as 0.
+template <typename T, bool EDGE, int N>
+__device__ __forceinline__ void loadN(const T* rowp, int gc, int ncols, bool row_ok, bool vec,
+                                      typename St<T>::V (&v)[N]) {
     using V = typename St<T>::V;
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = V(0);
+    if (EDGE && (!row_ok || gc < 0 || gc >= ncols)) return;
+    const T* p = rowp + gc;
+    if (vec && (!EDGE || gc + N - 1 < ncols)) {
+        if constexpr (N == 2) {
+            const Pack2<T> q = *reinterpret_cast<const Pack2<T>*>(p);
+            v[0] = St<T>::load(q.v[0]); v[1] = St<T>::load(q.v[1]);
+        } else {
+            const Pack4<T> q = *reinterpret_cast<const Pack4<T>*>(p);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = St<T>::load(q.v[i]);
+        }
+    } else {
+        v[0] = St<T>::load(p[0]);
+#pragma unroll
+        for (int i = 1; i < N; ++i)
+            if (!EDGE || gc + i < ncols) v[i] = St<T>::load(p[i]);
+    }
+}
+
+template <typename T, bool EDGE, int N>
+__device__ __forceinline__ void storeN(T* rowp, int gc, int ncols, bool vec, const typename St<T>::V (&v)[N]) {
+    if (EDGE && gc >= ncols) return;
+    T* p = rowp + gc;
+    if (vec && (!EDGE || gc + N - 1 < ncols)) {
+        if constexpr (N == 2) nt_store2(p, St<T>::store(v[0]), St<T>::store(v[1]));
+        else nt_store4(p, St<T>::store(v[0]), St<T>::store(v[1]), St<T>::store(v[2]), St<T>::store(v[3]));
+    } else {
+        p[0] = St<T>::store(v[0]);
+#pragma unroll
+        for (int i = 1; i < N; ++i)
+            if (!EDGE || gc + i < ncols) p[i] = St<T>::store(v[i]);
+    }
+}
+
+// Load the tile (halo included) into registers.
+template <int DIR, typename T, bool EDGE, int BPL, int K>
+__device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][Lay<BPL>::BX], const LevelParams& P,
+                                          const Geo& g, int gcE0, LaneRole lr) {
+    using V = typename St<T>::V;
+    using L = Lay<BPL>;
     const bool vec = P.vec != 0;
     const bool halo_lane = lr.l0 || lr.l63;
     if constexpr (DIR == kForward) {
@@ -661,19 +715,22 @@ __device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][kBX], const 
 #pragma unroll
         for (int r = 0; r < K; ++r) {
             const int row = 2 * (g.gr0 + r);
-            load4<T, EDGE>(in, P.in_pitch, row, 2 * g.gcL, P.h, P.w, vec, a[r][kL + 0], a[r][kL + 1], a[r][kR + 0],
-                           a[r][kR + 1]);
-            load4<T, EDGE>(in, P.in_pitch, row + 1, 2 * g.gcL, P.h, P.w, vec, a[r][kL + 2], a[r][kL + 3],
-                           a[r][kR + 2], a[r][kR + 3]);
+#pragma unroll
+            for (int q = 0; q < BPL / 2; ++q) {
+                const int c = 2 * g.gcL + 4 * q;
+                V* b0 = &a[r][8 * q];
+                load4<T, EDGE>(in, P.in_pitch, row, c, P.h, P.w, vec, b0[0], b0[1], b0[4], b0[5]);
+                load4<T, EDGE>(in, P.in_pitch, row + 1, c, P.h, P.w, vec, b0[2], b0[3], b0[6], b0[7]);
+            }
             if (EDGE) {
-                a[r][kE0 + 0] = a[r][kE0 + 1] = a[r][kE1 + 0] = a[r][kE1 + 1] = V(0);
-                a[r][kE0 + 2] = a[r][kE0 + 3] = a[r][kE1 + 2] = a[r][kE1 + 3] = V(0);
+#pragma unroll
+                for (int q = L::E0; q < L::BX; ++q) a[r][q] = V(0);
             }
             if (halo_lane) {
-                load4<T, EDGE>(in, P.in_pitch, row, 2 * gcE0, P.h, P.w, vec, a[r][kE0 + 0], a[r][kE0 + 1],
-                               a[r][kE1 + 0], a[r][kE1 + 1]);
-                load4<T, EDGE>(in, P.in_pitch, row + 1, 2 * gcE0, P.h, P.w, vec, a[r][kE0 + 2], a[r][kE0 + 3],
-                               a[r][kE1 + 2], a[r][kE1 + 3]);
+                load4<T, EDGE>(in, P.in_pitch, row, 2 * gcE0, P.h, P.w, vec, a[r][L::E0 + 0], a[r][L::E0 + 1],
+                               a[r][L::E1 + 0], a[r][L::E1 + 1]);
+                load4<T, EDGE>(in, P.in_pitch, row + 1, 2 * gcE0, P.h, P.w, vec, a[r][L::E0 + 2],
+                               a[r][L::E0 + 3], a[r][L::E1 + 2], a[r][L::E1 + 3]);
             }
         }
     } else {
@@ -685,32 +742,39 @@ __device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][kBX], const 
             const bool rE = gr >= 0 && gr < g.nEr;
             const bool rO = gr >= 0 && gr < g.nOr;
             const int64_t gre = rE ? gr : 0, gro = rO ? gr : 0;
-            const T* p0 = ll + gre * P.in_ll_pitch;
-            const T* p1 = det + gre * P.in_pitch + g.nEc;
-            const T* p2 = det + (g.nEr + gro) * P.in_pitch;
-            const T* p3 = det + (g.nEr + gro) * P.in_pitch + g.nEc;
-            load2<T, EDGE>(p0, g.gcL, g.nEc, rE, vec, a[r][kL + 0], a[r][kR + 0]);
-            load2<T, EDGE>(p1, g.gcL, g.nOc, rE, vec, a[r][kL + 1], a[r][kR + 1]);
-            load2<T, EDGE>(p2, g.gcL, g.nEc, rO, vec, a[r][kL + 2], a[r][kR + 2]);
-            load2<T, EDGE>(p3, g.gcL, g.nOc, rO, vec, a[r][kL + 3], a[r][kR + 3]);
+            const T* rows[4] = {ll + gre * P.in_ll_pitch, det + gre * P.in_pitch + g.nEc,
+                                det + (g.nEr + gro) * P.in_pitch, det + (g.nEr + gro) * P.in_pitch + g.nEc};
+            const int ncols[4] = {g.nEc, g.nOc, g.nEc, g.nOc};
+            const bool ok[4] = {rE, rE, rO, rO};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                V v[BPL];
+                loadN<T, EDGE, BPL>(rows[k], g.gcL, ncols[k], ok[k], vec, v);
+#pragma unroll
+                for (int b = 0; b < BPL; ++b) a[r][4 * b + k] = v[b];
+            }
             if (EDGE) {
 #pragma unroll
-                for (int q = kE0; q < kBX; ++q) a[r][q] = V(0);
+                for (int q = L::E0; q < L::BX; ++q) a[r][q] = V(0);
             }
             if (halo_lane) {
-                load2<T, EDGE>(p0, gcE0, g.nEc, rE, vec, a[r][kE0 + 0], a[r][kE1 + 0]);
-                load2<T, EDGE>(p1, gcE0, g.nOc, rE, vec, a[r][kE0 + 1], a[r][kE1 + 1]);
-                load2<T, EDGE>(p2, gcE0, g.nEc, rO, vec, a[r][kE0 + 2], a[r][kE1 + 2]);
-                load2<T, EDGE>(p3, gcE0, g.nOc, rO, vec, a[r][kE0 + 3], a[r][kE1 + 3]);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    V v[2];
+                    loadN<T, EDGE, 2>(rows[k], gcE0, ncols[k], ok[k], vec, v);
+                    a[r][L::E0 + k] = v[0];
+                    a[r][L::E1 + k] = v[1];
+                }
             }
         }
     }
 }
 
-// Store the core of the tile: the L and R blocks of every lane, halo rows dropped.
-template <int DIR, typename T, bool EDGE, int NW, int K>
-__device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][kBX], const LevelParams& P,
+// Store the core of the tile: the core blocks of every lane, halo rows dropped.
+template <int DIR, typename T, bool EDGE, int NW, int BPL, int K>
+__device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::BX], const LevelParams& P,
                                            const Geo& g, int wv) {
+    using V = typename St<T>::V;
     constexpr int kCoreBY = NW * K - 2 * kHalo;
     const bool vec = P.vec != 0;
 #pragma unroll
@@ -722,76 +786,96 @@ __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][kBX], const
         if constexpr (DIR == kForward) {
             T* ll = static_cast<T*>(P.out_ll);
             T* det = static_cast<T*>(P.out);
-            store2<T, EDGE>(ll + (int64_t)gr * P.out_ll_pitch, g.gcL, g.nEc, vec, a[r][kL + 0], a[r][kR + 0]);
-            store2<T, EDGE>(det + (int64_t)gr * P.out_pitch + g.nEc, g.gcL, g.nOc, vec, a[r][kL + 1], a[r][kR + 1]);
+            V v[4][BPL];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int b = 0; b < BPL; ++b) v[k][b] = a[r][4 * b + k];
+            storeN<T, EDGE, BPL>(ll + (int64_t)gr * P.out_ll_pitch, g.gcL, g.nEc, vec, v[0]);
+            storeN<T, EDGE, BPL>(det + (int64_t)gr * P.out_pitch + g.nEc, g.gcL, g.nOc, vec, v[1]);
             if (!EDGE || gr < g.nOr) {
-                store2<T, EDGE>(det + (int64_t)(g.nEr + gr) * P.out_pitch, g.gcL, g.nEc, vec, a[r][kL + 2],
-                                a[r][kR + 2]);
-                store2<T, EDGE>(det + (int64_t)(g.nEr + gr) * P.out_pitch + g.nEc, g.gcL, g.nOc, vec,
-                                a[r][kL + 3], a[r][kR + 3]);
+                storeN<T, EDGE, BPL>(det + (int64_t)(g.nEr + gr) * P.out_pitch, g.gcL, g.nEc, vec, v[2]);
+                storeN<T, EDGE, BPL>(det + (int64_t)(g.nEr + gr) * P.out_pitch + g.nEc, g.gcL, g.nOc, vec, v[3]);
             }
         } else {
             T* img = static_cast<T*>(P.out);
-            const int c = 2 * g.gcL;
-            store4<T, EDGE>(img, P.out_pitch, 2 * gr, c, P.h, P.w, vec, a[r][kL + 0], a[r][kL + 1], a[r][kR + 0],
-                            a[r][kR + 1]);
-            store4<T, EDGE>(img, P.out_pitch, 2 * gr + 1, c, P.h, P.w, vec, a[r][kL + 2], a[r][kL + 3],
-                            a[r][kR + 2], a[r][kR + 3]);
+#pragma unroll
+            for (int q = 0; q < BPL / 2; ++q) {
+                const int c = 2 * g.gcL + 4 * q;
+                const V* b0 = &a[r][8 * q];
+                store4<T, EDGE>(img, P.out_pitch, 2 * gr, c, P.h, P.w, vec, b0[0], b0[1], b0[4], b0[5]);
+                store4<T, EDGE>(img, P.out_pitch, 2 * gr + 1, c, P.h, P.w, vec, b0[2], b0[3], b0[6], b0[7]);
+            }
         }
     }
 }
 
+// LDS edge buffers of one work-group: one for predict-shaped steps (top rows
+// of the waves), one for update-shaped steps (bottom rows).
+template <typename V, int NW, int BPL> struct TileLds {
+    Vec4<V> t[NW][Lay<BPL>::NG][kLanes];
+    Vec4<V> s[NW][Lay<BPL>::NG][kLanes];
+};
+
 // One tile (tx, ty) of one level: load, the fused steps, store.  The LDS
 // edge buffers belong to the calling work-group.
-template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K>
-__device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty, Edge8<typename St<T>::V> (*bufT)[kLanes],
-                                          Edge8<typename St<T>::V> (*bufS)[kLanes], int lane, int wv) {
+template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K, int BPL>
+__device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
+                                          TileLds<typename St<T>::V, NW, BPL>& lds, int lane, int wv) {
     using V = typename St<T>::V;
+    using L = Lay<BPL>;
     constexpr int kCoreBY = NW * K - 2 * kHalo;
     Geo g;
     g.nEr = (P.h + 1) >> 1; g.nOr = P.h >> 1;
     g.nEc = (P.w + 1) >> 1; g.nOc = P.w >> 1;
-    const int cb0 = tx * kTileCoreBX, rb0 = ty * kCoreBY;
+    const int cb0 = tx * L::CORE_BX, rb0 = ty * kCoreBY;
     LaneRole lr;
     lr.l0 = lane == 0;
     lr.l63 = lane == kLanes - 1;
-    g.gcL = cb0 + 2 * lane;
+    g.gcL = cb0 + BPL * lane;
     g.gr0 = rb0 - kHalo + wv * K;
-    const int gcE0 = lr.l0 ? cb0 - kHalo : cb0 + kTileCoreBX;
-    const int gc[4] = {g.gcL, g.gcL + 1, gcE0, gcE0 + 1};
+    const int gcE0 = lr.l0 ? cb0 - kHalo : cb0 + L::CORE_BX;
+    int gc[L::NB];
+#pragma unroll
+    for (int b = 0; b < BPL; ++b) gc[b] = g.gcL + b;
+    gc[BPL] = gcE0;
+    gc[BPL + 1] = gcE0 + 1;
     // Interior tile: every loaded block has all four components and no
     // neighbour index of the core's dependency cone needs clamping.
     const bool interior = rb0 - kHalo >= 0 && cb0 - kHalo >= 0 &&
-                          rb0 + kCoreBY + kHalo <= g.nOr && cb0 + kTileCoreBX + kHalo <= g.nOc;
-    V a[K][kBX];
+                          rb0 + kCoreBY + kHalo <= g.nOr && cb0 + L::CORE_BX + kHalo <= g.nOc;
+    V a[K][L::BX];
     if (interior) {
-        load_tile<DIR, T, false>(a, P, g, gcE0, lr);
-        run<DIR, WAV, false, SPLIT, NW>(a, bufT, bufS, lane, wv, g, gc, lr);
-        store_tile<DIR, T, false, NW>(a, P, g, wv);
+        load_tile<DIR, T, false, BPL>(a, P, g, gcE0, lr);
+        run<DIR, WAV, false, SPLIT, NW, BPL>(a, lds.t, lds.s, lane, wv, g, gc);
+        store_tile<DIR, T, false, NW, BPL>(a, P, g, wv);
     } else {
-        load_tile<DIR, T, true>(a, P, g, gcE0, lr);
-        run<DIR, WAV, true, false, NW>(a, bufT, bufS, lane, wv, g, gc, lr);
-        store_tile<DIR, T, true, NW>(a, P, g, wv);
+        load_tile<DIR, T, true, BPL>(a, P, g, gcE0, lr);
+        run<DIR, WAV, true, false, NW, BPL>(a, lds.t, lds.s, lane, wv, g, gc);
+        store_tile<DIR, T, true, NW, BPL>(a, P, g, wv);
     }
 }
 
-template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K>
+template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K, int BPL>
 __global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
     using V = typename St<T>::V;
-    __shared__ Edge8<V> bufT[NW][kLanes];
-    __shared__ Edge8<V> bufS[NW][kLanes];
+    __shared__ TileLds<V, NW, BPL> lds;
     const int lane = threadIdx.x & (kLanes - 1);
     // the wave index is uniform: keep it (and every row address) in SGPRs
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
-    // Work-groups are dealt round-robin over the 8 XCDs; give each XCD a
-    // contiguous run of tiles (row-major) so neighbouring halos share its L2.
+    // Work-groups are dealt round-robin over the 8 XCDs.  XCD x takes chunks
+    // x, x + 8, x + 16, ... of kRemapRows whole tile rows: horizontal halo
+    // re-reads stay in that XCD's L2 (and vertical ones within a chunk),
+    // while the 8 XCDs work on adjacent chunks, so the image is swept by
+    // one narrow window (8 chunks tall) rather than 8 distant ones.
     const int nt = P.tiles_x * P.tiles_y;
-    const int per = (nt + 7) >> 3;
-    const int t = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    const int chunk = kRemapRows * P.tiles_x;
+    const int j = (int)(blockIdx.x >> 3);
+    const int t = ((j / chunk) * 8 + (int)(blockIdx.x & 7)) * chunk + j % chunk;
     if (t >= nt) return;                          // uniform over the work-group
     const int ty = t / P.tiles_x;
     const int tx = t - ty * P.tiles_x;
-    tile_body<DIR, WAV, T, SPLIT, NW, K>(P, tx, ty, bufT, bufS, lane, wv);
+    tile_body<DIR, WAV, T, SPLIT, NW, K, BPL>(P, tx, ty, lds, lane, wv);
 }
 
 // ===========================================================================

@@ -5,11 +5,15 @@
 namespace dwt2 {
 namespace kern {
 
-template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K>
+template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K, int BPL>
 hipError_t launch_shape(const LevelParams& p, hipStream_t s) {
-    const int nt = p.tiles_x * p.tiles_y;
-    const int grid = ((nt + 7) >> 3) * 8;
-    hipLaunchKernelGGL((level_kernel<DIR, WAV, T, SPLIT, NW, K>), dim3(grid), dim3(NW * kLanes), 0, s, p);
+    // a multiple of 8 chunks of kRemapRows tile rows (see level_kernel)
+    const int64_t chunk = (int64_t)kRemapRows * p.tiles_x;
+    const int64_t chunks = (p.tiles_y + kRemapRows - 1) / kRemapRows;
+    const int64_t grid = (chunks + 7) / 8 * 8 * chunk;
+    if (grid > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((level_kernel<DIR, WAV, T, SPLIT, NW, K, BPL>), dim3((unsigned)grid), dim3(NW * kLanes), 0, s,
+                       p);
     return hipGetLastError();
 }
 
@@ -27,7 +31,8 @@ hipError_t launch(int cfg, const LevelParams& p, hipStream_t s) {
 #define DWT2_CFG(i)                                                                              \
     case i:                                                                                      \
         if constexpr (kConfigs[i].algo == kAlgoTile)                                             \
-            return launch_shape<DIR, WAV, T, SPLIT, kConfigs[i].waves, kConfigs[i].rows>(p, s);  \
+            return launch_shape<DIR, WAV, T, SPLIT, kConfigs[i].waves, kConfigs[i].rows,         \
+                                kConfigs[i].bpl>(p, s);                                          \
         else                                                                                     \
             return launch_stream<DIR, WAV, T, SPLIT, kConfigs[i].waves, kConfigs[i].rows>(p, s);
     switch (cfg) {

@@ -1,4 +1,5 @@
-// Host check of the batched work plan (dwt2_batch_plan.h): on random batches
+// Host check of the tile work plans (dwt2_batch_plan.h, and the level
+// kernel's tile remap): on random batches
 // of uneven images, every tile of every image at every level is covered
 // exactly once by the per-level grids (with the XCD remap of the batched
 // level kernel), the work tables fit below the LL area, and every
@@ -11,13 +12,13 @@
 #include <random>
 #include "dwt2_batch_plan.h"
 using namespace dwt2;
-int run(const std::vector<int>& H, const std::vector<int>& W, int levels, int core, size_t es) {
+int run(const std::vector<int>& H, const std::vector<int>& W, int levels, int cx, int core, size_t es) {
     int count = H.size(); int bad = 0;
     BatchLayout L = batch_layout(count, levels);
     std::vector<uint32_t> off((size_t)levels * (count + 1));
     for (int l = 0; l < levels; ++l) {
         uint32_t c = 0;
-        for (int i = 0; i < count; ++i) { off[l*(count+1)+i] = c; c += (uint32_t)level_tile_count(H[i], W[i], l, core); }
+        for (int i = 0; i < count; ++i) { off[l*(count+1)+i] = c; c += (uint32_t)level_tile_count(H[i], W[i], l, cx, core); }
         off[l*(count+1)+count] = c;
     }
     size_t llsum = 0; std::vector<size_t> llo(count);
@@ -27,11 +28,13 @@ int run(const std::vector<int>& H, const std::vector<int>& W, int levels, int co
     if (L.off_ll_off + 8*(size_t)count > L.off_ll) bad++;
     for (int l = 0; l < levels; ++l) {
         uint32_t total = off[l*(count+1)+count];
-        uint32_t grid = (total + 7) / 8 * 8; uint32_t per = grid >> 3;
+        const uint32_t chunks = (total + kBatchChunk - 1) / kBatchChunk;
+        const uint32_t grid = (chunks + 7) / 8 * 8 * kBatchChunk;
         std::vector<std::vector<int>> seen(count);
-        for (int i = 0; i < count; ++i) seen[i].assign(level_tile_count(H[i], W[i], l, core), 0);
+        for (int i = 0; i < count; ++i) seen[i].assign(level_tile_count(H[i], W[i], l, cx, core), 0);
         for (uint32_t b = 0; b < grid; ++b) {
-            uint32_t t = (b & 7) * per + (b >> 3);
+            const uint32_t j = b >> 3;
+            const uint32_t t = ((j / kBatchChunk) * 8 + (b & 7)) * kBatchChunk + j % kBatchChunk;
             if (t >= total) continue;
             const uint32_t* o = &off[l*(count+1)];
             int lo = 0, hi = count;
@@ -59,9 +62,33 @@ int run(const std::vector<int>& H, const std::vector<int>& W, int levels, int co
     }
     return bad;
 }
+// The single-image level kernel's grid and tile remap (chunks of
+// kRemapRows tile rows dealt over 8 XCDs) cover every tile exactly once.
+int check_level_mapping() {
+    int bad = 0;
+    for (int tiles_x = 1; tiles_x <= 40; tiles_x += 3)
+        for (int tiles_y = 1; tiles_y <= 700; tiles_y += 7) {
+            const int64_t chunk = (int64_t)kRemapRows * tiles_x;
+            const int64_t chunks = (tiles_y + kRemapRows - 1) / kRemapRows;
+            const int64_t grid = (chunks + 7) / 8 * 8 * chunk;
+            const int nt = tiles_x * tiles_y;
+            std::vector<int> seen(nt, 0);
+            for (int64_t b = 0; b < grid; ++b) {
+                const int j = (int)(b >> 3);
+                const int t = (int)(((j / chunk) * 8 + (b & 7)) * chunk + j % chunk);
+                if (t < 0) { bad++; continue; }
+                if (t < nt) seen[t]++;
+            }
+            for (int v : seen) if (v != 1) { bad++; break; }
+        }
+    return bad;
+}
 int main() {
+    if (int b = check_level_mapping()) { printf("level mapping bad %d\n", b); return 1; }
     std::mt19937 rng(7); int bad = 0, cases = 0;
-    for (int core : {12, 28}) for (size_t es : {2, 4}) for (int rep = 0; rep < 200; ++rep) {
+    const int shapes[][2] = {{128, 12}, {128, 28}, {256, 12}, {128, 20}};
+    for (const auto& sh : shapes) for (size_t es : {2, 4}) for (int rep = 0; rep < 150; ++rep) {
+        const int cx = sh[0], core = sh[1];
         int count = 1 + rng() % 300; std::vector<int> H(count), W(count);
         int lo = 2 + rng() % 64, hi = lo + rng() % 3000;
         for (int i = 0; i < count; ++i) { H[i] = lo + rng() % (hi - lo + 1); W[i] = lo + rng() % (hi - lo + 1); }
@@ -74,7 +101,7 @@ int main() {
         }
         if (ml < 1) continue;
         int levels = 1 + rng() % ml;
-        bad += run(H, W, levels, core, es); ++cases;
+        bad += run(H, W, levels, cx, core, es); ++cases;
     }
     printf("cases %d bad %d\n", cases, bad);
     return bad != 0;

@@ -33,7 +33,7 @@ def uneven(count, lo, hi, seed, odd=False):
 
 
 @pytest.mark.parametrize("tdt", [torch.float32, torch.bfloat16])
-@pytest.mark.parametrize("config", [0, 1])
+@pytest.mark.parametrize("config", [0, 1, 2])
 def test_batched_equals_single(tdt, config):
     shapes, imgs = uneven(24, 64, 700, seed=1, odd=True)
     xs = [torch.from_numpy(x).to(dev()).to(tdt) for x in imgs]

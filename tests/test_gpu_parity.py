@@ -218,8 +218,12 @@ def test_kernel_configs_bit_identical():
     """Each coefficient's arithmetic does not depend on the tiling, so every
     kernel configuration (tile shapes, streaming strips and segments) must
     give bit-identical results (a halo, pipeline or race bug breaks it)."""
+    # (600, 2056) and (520, 2056): subband widths a multiple of 4, so the
+    # vector paths of every tile width run, with interior tiles in between
     cases = [("cdf97", torch.float32, (517, 1283), 3, False), ("cdf97", torch.float32, (1000, 700), 1, True),
-             ("cdf97", torch.bfloat16, (300, 260), 2, False), ("cdf53", torch.int32, (613, 901), 4, False)]
+             ("cdf97", torch.bfloat16, (300, 260), 2, False), ("cdf53", torch.int32, (613, 901), 4, False),
+             ("cdf97", torch.float32, (600, 2056), 2, False), ("cdf97", torch.float32, (600, 2056), 1, True),
+             ("cdf97", torch.bfloat16, (260, 2056), 1, False), ("cdf53", torch.int32, (520, 2056), 2, False)]
     for wav, tdt, (h, w), lv, split in cases:
         if wav == "cdf53":
             x = gpu(workloads.pixels_u8(h, w, seed=4))
@@ -230,8 +234,13 @@ def test_kernel_configs_bit_identical():
         for sh in range(1, d.DWT2_NUM_KERNEL_CONFIGS):
             say("kernel config", sh, wav, tdt, (h, w), lv, split)
             f = d.fwd(x, wav, lv, split=split, config=sh)
-            if split:   # the split runs only away from the border
-                assert rel_err(host(f), host(ref_f)) <= 1e-6
+            if split:
+                # The split (P = P0 + P1, U = U0 + U1) runs in interior tiles
+                # only, and which tiles are interior depends on the tile
+                # shape; split and fused arithmetic differ by rounding, so
+                # the two results agree to the bar both meet against the
+                # oracle (1e-5 relative max-abs), not bit for bit.
+                assert rel_err(host(f), host(ref_f)) <= 1e-5
             else:
                 assert torch.equal(f, ref_f)
                 assert torch.equal(d.inv(f, wav, lv, config=sh), ref_i)
