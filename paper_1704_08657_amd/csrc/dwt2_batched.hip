@@ -85,7 +85,7 @@ batched_level_kernel(const dwt2_image* imgs, int count, int levels, int l, unsig
     using V = typename St<T>::V;
     constexpr int kCoreBY = NW * K - 2 * kHalo;
     constexpr size_t es = sizeof(T);
-    __shared__ TileLds<V, NW, BPL> lds;
+    __shared__ TileLds<V, NW, BPL, K> lds;
     const int lane = threadIdx.x & (kLanes - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
     const BatchLayout L = batch_layout(count, levels);

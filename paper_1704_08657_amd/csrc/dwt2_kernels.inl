@@ -139,7 +139,8 @@ enum Kind : int {
     kIntInv = 5      // reversible 5/3 inverse
 };
 
-template <typename V> struct Vec4 { V a, b, c, d; };
+template <typename V> struct alignas(4 * sizeof(V)) Vec4 { V a, b, c, d; };
+template <typename V> struct alignas(2 * sizeof(V)) Vec2 { V a, b; };
 
 // ---- predict-shaped block update (reads right / down / down-right) --------
 // Operands: own x0..x3; right: x0R, x2R; down: x0D, x1D; diagonal x0DR.
@@ -286,113 +287,126 @@ __device__ __forceinline__ void minus_block(V& x0, V& x1, V& x2, V& x3,
 }
 
 // ---------------------------------------------------------------------------
-// Tile kernel.  A lane holds, for each of its K block rows, BPL + 2 blocks:
-// B0 .. B(BPL-1) = tile columns BPL*lane .. BPL*lane + BPL - 1 (the tile's
-// 64 * BPL output columns), and a halo pair E0, E1 that only lanes 0 and 63
-// use: tile columns -2, -1 (lane 0) and 64*BPL, 64*BPL + 1 (lane 63).  The
-// output columns of a tile are then aligned to whole subband rows of 64 * BPL
-// samples, so every store covers whole cache lines; the halo pair costs
-// extra arithmetic (2 of the lane's BPL + 2 blocks), which is hidden behind
-// memory.  a[r][4 b + k] = component x_k of block b (b = BPL: E0, BPL+1: E1).
+// Tile kernel.  A lane holds BPL horizontally adjacent blocks (tile columns
+// BPL*lane .. BPL*lane + BPL - 1) for each of its K block rows, so a wave
+// covers the tile's 64 * BPL output columns, aligned to whole subband rows
+// of 64 * BPL samples: every store covers whole cache lines.
+// a[r][4 b + k] = component x_k of core block b of row r.
+//
+// The horizontal halo (two block columns on each side) is held in one more
+// register pair, e[8], with its rows spread over lanes: lane q < 32 holds
+// the two halo blocks of the wave's block row r = q & 15 (if r < K) on side
+// q >> 4 (side 0: tile columns -2, -1; side 1: 64*BPL, 64*BPL + 1);
+// e[0..3] = x0..x3 of the first block, e[4..7] of the second.  A fused step
+// thus updates the halo with two block updates for the whole wave instead of
+// two per row.  Vertical neighbours of halo blocks are the adjacent lanes
+// (DPP row shifts); the values that cross between the halo lanes and the
+// first / last lane of the core go through a small per-wave LDS area.
 // ---------------------------------------------------------------------------
 template <int BPL> struct Lay {
     static_assert(BPL == 2 || BPL == 4, "2 or 4 blocks per lane");
-    static constexpr int NB = BPL + 2;            // blocks per lane and row
-    static constexpr int BX = 4 * NB;             // values per register row
-    static constexpr int E0 = 4 * BPL, E1 = 4 * BPL + 4;
-    static constexpr int LAST = 4 * (BPL - 1);    // last core block
-    static constexpr int NG = NB / 2;             // Vec4 groups of one edge row (2 values per block)
+    static constexpr int BX = 4 * BPL;            // values per register row
+    static constexpr int LAST = 4 * (BPL - 1);    // last block
+    static constexpr int NG = BPL / 2;            // Vec4 groups of one edge row (2 values per block)
     static constexpr int CORE_BX = kLanes * BPL;  // output block columns of a tile
 };
 
-struct LaneRole {
-    bool l0, l63;
+// lane i <- lane i+1 (next) or i-1 (prev) within its row of 16 lanes (0 in
+// a lane without a source lane in its row).
+__device__ __forceinline__ int row_next(int v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x101 /* row_shl:1 */, 0xf, 0xf, true);
+}
+__device__ __forceinline__ int row_prev(int v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x111 /* row_shr:1 */, 0xf, 0xf, true);
+}
+__device__ __forceinline__ float row_next(float v) { return __int_as_float(row_next(__float_as_int(v))); }
+__device__ __forceinline__ float row_prev(float v) { return __int_as_float(row_prev(__float_as_int(v))); }
+
+// LDS of one work-group.  t: the top block row (x0, x1) of every wave, for
+// the wave above; s: the bottom row (x2, x3), for the wave below; both
+// group-major (buf[wave][group][lane], 16-byte accesses contiguous across
+// the wave).  et / es: the same for the halo rows (per side: first block,
+// second block).  Wave w publishes to t[w], et[w], s[w + 1], es[w + 1] and
+// reads t[w + 1], et[w + 1], s[w], es[w]: the slots t[NW], s[0] (and the
+// halo ones) hold zeros for the outermost waves, which only reach tile rows
+// outside the core (a predict-shaped step carries values up one row, an
+// update-shaped one down one row, and the tile's 2-row halo absorbs the two
+// of each).  col / hal: per-wave exchange
+// between the core's edge lane and the halo lanes, indexed by block row.
+template <typename V, int NW, int BPL, int K> struct TileLds {
+    static_assert(K % 2 == 0 && K <= 16, "K even, at most 16 rows per wave");
+    Vec4<V> t[NW + 1][Lay<BPL>::NG][kLanes];
+    Vec4<V> s[NW + 1][Lay<BPL>::NG][kLanes];
+    Vec4<V> et[NW + 1][2];
+    Vec4<V> es[NW + 1][2];
+    V col[NW][2][16];
+    V hal[NW][2][16];
 };
 
-// Operands of a predict-shaped step for the blocks of one row, all taken
-// before the step: right neighbour (x0R, x2R), lower (x0D, x1D), lower-right (x0DR).
-template <typename V, int NB> struct PlusOps { V x0R[NB], x2R[NB], x0D[NB], x1D[NB], x0DR[NB]; };
+// Operands of a predict-shaped step for N blocks, all taken before the step:
+// right neighbour (x0R, x2R), lower (x0D, x1D), lower-right (x0DR).
+template <typename V, int N> struct PlusOps { V x0R[N], x2R[N], x0D[N], x1D[N], x0DR[N]; };
 // Operands of an update-shaped step: left (x1l, x3l), upper (x2u, x3u), upper-left (x3ul).
-template <typename V, int NB> struct MinusOps { V x1l[NB], x3l[NB], x2u[NB], x3u[NB], x3ul[NB]; };
+template <typename V, int N> struct MinusOps { V x1l[N], x3l[N], x2u[N], x3u[N], x3ul[N]; };
 
-// cur: the row; dn: the row below (x0, x1 used); dnRB0: the right lane's
-// B0.x0 of the row below (E0.x0 in lane 63).  The right neighbour of the
-// last core block is the next lane's B0, or E0 in lane 63; the right
-// neighbour of E1 is B0 (block -1 -> 0 in lane 0; in lane 63, block
-// 64*BPL + 1 is outermost halo and any value will do).
+// cur: the row; dn: the row below (x0, x1 used).  The right neighbour of the
+// last block is the next lane's first block: R0, R2 are that block's x0, x2
+// for this row and RD0 its x0 for the row below (lane 63: the halo column
+// 64*BPL instead).
 template <int BPL, typename V>
-__device__ __forceinline__ void gather_plus(const V (&cur)[Lay<BPL>::BX], const V (&dn)[Lay<BPL>::BX], V dnRB0,
-                                            PlusOps<V, Lay<BPL>::NB>& o) {
+__device__ __forceinline__ void gather_plus(const V (&cur)[Lay<BPL>::BX], const V (&dn)[Lay<BPL>::BX], V R0, V R2,
+                                            V RD0, PlusOps<V, BPL>& o) {
     using L = Lay<BPL>;
 #pragma unroll
-    for (int b = 0; b + 1 < BPL; ++b) {                                      // B(b) -> B(b+1)
+    for (int b = 0; b + 1 < BPL; ++b) {
         o.x0R[b] = cur[4 * b + 4]; o.x2R[b] = cur[4 * b + 6];
         o.x0D[b] = dn[4 * b]; o.x1D[b] = dn[4 * b + 1]; o.x0DR[b] = dn[4 * b + 4];
     }
-    constexpr int b = BPL - 1;                                               // -> next lane's B0
-    o.x0R[b] = from_right_or(cur[L::E0 + 0], cur[0]);
-    o.x2R[b] = from_right_or(cur[L::E0 + 2], cur[2]);
-    o.x0D[b] = dn[L::LAST]; o.x1D[b] = dn[L::LAST + 1]; o.x0DR[b] = dnRB0;
-    o.x0R[BPL] = cur[L::E1 + 0]; o.x2R[BPL] = cur[L::E1 + 2];                // E0 -> E1
-    o.x0D[BPL] = dn[L::E0]; o.x1D[BPL] = dn[L::E0 + 1]; o.x0DR[BPL] = dn[L::E1];
-    o.x0R[BPL + 1] = cur[0]; o.x2R[BPL + 1] = cur[2];                        // E1 -> B0
-    o.x0D[BPL + 1] = dn[L::E1]; o.x1D[BPL + 1] = dn[L::E1 + 1]; o.x0DR[BPL + 1] = dn[0];
+    constexpr int b = BPL - 1;
+    o.x0R[b] = R0; o.x2R[b] = R2;
+    o.x0D[b] = dn[L::LAST]; o.x1D[b] = dn[L::LAST + 1]; o.x0DR[b] = RD0;
 }
 
-// cur: the row; up: the row above (x2, x3 used); upLB3: the left lane's
-// last core block's x3 of the row above (E1.x3 in lane 0).  The left
-// neighbour of B0 is the previous lane's last core block, or E1 in lane 0;
-// the left neighbour of E0 is the last core block (block 64*BPL -> 64*BPL - 1
-// in lane 63; in lane 0, block -2 is outermost halo).
+// cur: the row; up: the row above (x2, x3 used).  The left neighbour of the
+// first block is the previous lane's last block: L1, L3 are that block's
+// x1, x3 for this row and LU3 its x3 for the row above (lane 0: the halo
+// column -1 instead).
 template <int BPL, typename V>
-__device__ __forceinline__ void gather_minus(const V (&cur)[Lay<BPL>::BX], const V (&up)[Lay<BPL>::BX], V upLB3,
-                                             MinusOps<V, Lay<BPL>::NB>& o) {
-    using L = Lay<BPL>;
-    o.x1l[0] = from_left_or(cur[L::E1 + 1], cur[L::LAST + 1]);              // B0 <- previous lane
-    o.x3l[0] = from_left_or(cur[L::E1 + 3], cur[L::LAST + 3]);
-    o.x2u[0] = up[2]; o.x3u[0] = up[3]; o.x3ul[0] = upLB3;
+__device__ __forceinline__ void gather_minus(const V (&cur)[Lay<BPL>::BX], const V (&up)[Lay<BPL>::BX], V L1, V L3,
+                                             V LU3, MinusOps<V, BPL>& o) {
+    o.x1l[0] = L1; o.x3l[0] = L3;
+    o.x2u[0] = up[2]; o.x3u[0] = up[3]; o.x3ul[0] = LU3;
 #pragma unroll
-    for (int b = 1; b < BPL; ++b) {                                          // B(b) <- B(b-1)
+    for (int b = 1; b < BPL; ++b) {
         o.x1l[b] = cur[4 * b - 3]; o.x3l[b] = cur[4 * b - 1];
         o.x2u[b] = up[4 * b + 2]; o.x3u[b] = up[4 * b + 3]; o.x3ul[b] = up[4 * b - 1];
     }
-    o.x1l[BPL] = cur[L::LAST + 1]; o.x3l[BPL] = cur[L::LAST + 3];            // E0 <- last core block
-    o.x2u[BPL] = up[L::E0 + 2]; o.x3u[BPL] = up[L::E0 + 3]; o.x3ul[BPL] = up[L::LAST + 3];
-    o.x1l[BPL + 1] = cur[L::E0 + 1]; o.x3l[BPL + 1] = cur[L::E0 + 3];        // E1 <- E0
-    o.x2u[BPL + 1] = up[L::E1 + 2]; o.x3u[BPL + 1] = up[L::E1 + 3]; o.x3ul[BPL + 1] = up[L::E0 + 3];
 }
 
-// EMASK selects the halo blocks a step must update (bit 0: E0, bit 1: E1).
-// Going backwards from the tile's output columns, a predict-shaped step
-// widens the columns the previous stage must provide by one to the right, an
-// update-shaped step by one to the left; a halo block is updated only at the
-// steps whose stage is needed at its column (-2, -1 in lane 0; 64*BPL,
-// 64*BPL + 1 in lane 63).  Skipped halo values are never read by a needed value.
-template <int KIND, int EMASK, bool EX, bool EY, int BPL, typename V>
-__device__ __forceinline__ void apply_plus(V (&cur)[Lay<BPL>::BX], const PlusOps<V, Lay<BPL>::NB>& o,
-                                           const int (&gc)[Lay<BPL>::NB], int gr, const Geo& g, float c) {
+// Apply a step to blocks 0 .. N-1 of v (v[4 b + k] = x_k of block b) whose
+// bit is set in MASK; gc[b]: block column, gr: block row.
+template <int KIND, int MASK, bool EX, bool EY, int N, typename V>
+__device__ __forceinline__ void apply_plus(V (&v)[4 * N], const PlusOps<V, N>& o, const int (&gc)[N], int gr,
+                                           const Geo& g, float c) {
 #pragma unroll
-    for (int b = 0; b < Lay<BPL>::NB; ++b)
-        if (b < BPL || (EMASK >> (b - BPL)) & 1)
-            plus_block<KIND, EX, EY>(cur[4 * b], cur[4 * b + 1], cur[4 * b + 2], cur[4 * b + 3], o.x0R[b],
-                                     o.x2R[b], o.x0D[b], o.x1D[b], o.x0DR[b], gc[b], gr, g, c);
+    for (int b = 0; b < N; ++b)
+        if ((MASK >> b) & 1)
+            plus_block<KIND, EX, EY>(v[4 * b], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3], o.x0R[b], o.x2R[b],
+                                     o.x0D[b], o.x1D[b], o.x0DR[b], gc[b], gr, g, c);
 }
-
-template <int KIND, int EMASK, bool EX, bool EY, int BPL, typename V>
-__device__ __forceinline__ void apply_minus(V (&cur)[Lay<BPL>::BX], const MinusOps<V, Lay<BPL>::NB>& o,
-                                            const int (&gc)[Lay<BPL>::NB], int gr, const Geo& g, float c) {
+template <int KIND, int MASK, bool EX, bool EY, int N, typename V>
+__device__ __forceinline__ void apply_minus(V (&v)[4 * N], const MinusOps<V, N>& o, const int (&gc)[N], int gr,
+                                            const Geo& g, float c) {
 #pragma unroll
-    for (int b = 0; b < Lay<BPL>::NB; ++b)
-        if (b < BPL || (EMASK >> (b - BPL)) & 1)
-            minus_block<KIND, EX, EY>(cur[4 * b], cur[4 * b + 1], cur[4 * b + 2], cur[4 * b + 3], o.x1l[b],
-                                      o.x3l[b], o.x2u[b], o.x3u[b], o.x3ul[b], gc[b], gr, g, c);
+    for (int b = 0; b < N; ++b)
+        if ((MASK >> b) & 1)
+            minus_block<KIND, EX, EY>(v[4 * b], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3], o.x1l[b], o.x3l[b],
+                                      o.x2u[b], o.x3u[b], o.x3ul[b], gc[b], gr, g, c);
 }
 
-// Edge rows exchanged between the waves of a tile: x0, x1 of the top row
-// (read by predict-shaped steps of the wave above) and x2, x3 of the bottom
-// row (read by update-shaped steps of the wave below), for every block of a
-// lane, as NG groups of four values.  Group-major layout buf[wave][group][lane]:
-// the 16-byte accesses of a wave are contiguous, free of bank conflicts.
+// Edge rows of the core for the neighbouring waves: x_k0, x_k0+1 of every
+// block (k0 = 0: top row for predict-shaped steps, 2: bottom row for
+// update-shaped steps).
 template <int BPL, typename V>
 __device__ __forceinline__ void publish_row(const V (&row)[Lay<BPL>::BX], int k0, Vec4<V> (*buf)[kLanes],
                                             int lane) {
@@ -410,77 +424,192 @@ __device__ __forceinline__ void fetch_row(V (&row)[Lay<BPL>::BX], int k0, Vec4<V
     }
 }
 
-// Predict-shaped step over the tile: rows top to bottom, so row r+1 is still
-// unmodified when row r reads it.
-template <int KIND, int EMASK, bool EDGE, int NW, int BPL, int K, typename V>
-__device__ __forceinline__ void plus_step(V (&a)[K][Lay<BPL>::BX], Vec4<V> (*buf)[Lay<BPL>::NG][kLanes], int lane,
-                                          int wv, const Geo& g, const int (&gc)[Lay<BPL>::NB], float c) {
-    using L = Lay<BPL>;
+// Per-lane geometry of a tile step.
+template <int BPL> struct TileGeo {
+    int gc[BPL];      // block columns of the lane's core blocks
+    int ge[2];        // block columns of the lane's halo blocks
+    int gre;          // block row of the lane's halo row
+    int re;           // halo row within the wave (lane & 15)
+};
+
+// Before the barrier of a predict-shaped step: the wave's top rows (core and
+// halo) for the wave above, and the exchange columns for this wave: core
+// column 0 (x0, x2 of every row, read by the left halo lanes) and halo
+// column 64*BPL (x0, x2, read by lane 63).
+template <int NW, int BPL, int K, typename V>
+__device__ __forceinline__ void publish_plus(const V (&a)[K][Lay<BPL>::BX], const V (&e)[8],
+                                             TileLds<V, NW, BPL, K>& L, int lane, int wv) {
+    publish_row<BPL>(a[0], 0, L.t[wv], lane);
+    if (lane < 32 && (lane & 15) == 0) L.et[wv][lane >> 4] = Vec4<V>{e[0], e[1], e[4], e[5]};
+    if (lane == 0) {
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
-        PlusOps<V, L::NB> o;
-        if (r + 1 < K) {
-            gather_plus<BPL>(a[r], a[r + 1], from_right_or(a[r + 1][L::E0], a[r + 1][0]), o);
-        } else if (wv + 1 < NW) {
-            V dn[L::BX];
-            fetch_row<BPL>(dn, 0, buf[wv + 1], lane);
-            gather_plus<BPL>(a[r], dn, from_right_or(dn[L::E0], dn[0]), o);
-        } else {                                  // below the tile: halo, any finite value
-            gather_plus<BPL>(a[r], a[r], from_right_or(a[r][L::E0], a[r][0]), o);
+        for (int r = 0; r < K; r += 2) {
+            *reinterpret_cast<Vec2<V>*>(&L.col[wv][0][r]) = Vec2<V>{a[r][0], a[r + 1][0]};
+            *reinterpret_cast<Vec2<V>*>(&L.col[wv][1][r]) = Vec2<V>{a[r][2], a[r + 1][2]};
         }
-        apply_plus<KIND, EMASK, EDGE, EDGE, BPL>(a[r], o, gc, g.gr0 + r, g, c);
+    }
+    if (lane >= 16 && lane < 16 + K) {
+        L.hal[wv][0][lane - 16] = e[0];
+        L.hal[wv][1][lane - 16] = e[2];
     }
 }
 
-// Update-shaped step over the tile: rows bottom to top.
+// Before the barrier of an update-shaped step: the bottom rows for the wave
+// below, core column 64*BPL - 1 (x1, x3, read by the right halo lanes) and
+// halo column -1 (x1, x3, read by lane 0).
+template <int NW, int BPL, int K, typename V>
+__device__ __forceinline__ void publish_minus(const V (&a)[K][Lay<BPL>::BX], const V (&e)[8],
+                                              TileLds<V, NW, BPL, K>& L, int lane, int wv) {
+    using Ly = Lay<BPL>;
+    publish_row<BPL>(a[K - 1], 2, L.s[wv + 1], lane);
+    if (lane < 32 && (lane & 15) == K - 1) L.es[wv + 1][lane >> 4] = Vec4<V>{e[2], e[3], e[6], e[7]};
+    if (lane == kLanes - 1) {
+#pragma unroll
+        for (int r = 0; r < K; r += 2) {
+            *reinterpret_cast<Vec2<V>*>(&L.col[wv][0][r]) = Vec2<V>{a[r][Ly::LAST + 1], a[r + 1][Ly::LAST + 1]};
+            *reinterpret_cast<Vec2<V>*>(&L.col[wv][1][r]) = Vec2<V>{a[r][Ly::LAST + 3], a[r + 1][Ly::LAST + 3]};
+        }
+    }
+    if (lane < K) {
+        L.hal[wv][0][lane] = e[5];
+        L.hal[wv][1][lane] = e[7];
+    }
+}
+
+// Predict-shaped step over the tile (after the barrier).  Core rows top to
+// bottom, so row r+1 is still unmodified when row r reads it; the halo lanes
+// read only values taken before the step.
 template <int KIND, int EMASK, bool EDGE, int NW, int BPL, int K, typename V>
-__device__ __forceinline__ void minus_step(V (&a)[K][Lay<BPL>::BX], Vec4<V> (*buf)[Lay<BPL>::NG][kLanes], int lane,
-                                           int wv, const Geo& g, const int (&gc)[Lay<BPL>::NB], float c) {
-    using L = Lay<BPL>;
+__device__ __forceinline__ void plus_step(V (&a)[K][Lay<BPL>::BX], V (&e)[8], TileLds<V, NW, BPL, K>& L, int lane,
+                                          int wv, const Geo& g, const TileGeo<BPL>& tg, float c) {
+    using Ly = Lay<BPL>;
+    // halo operands first (e is still at the previous stage)
+    PlusOps<V, 2> h;
+    {
+        const int side = (lane >> 4) & 1;
+        const Vec4<V> q = L.et[wv + 1][side];
+        const V n0 = q.a, n1 = q.b, n2 = q.c, n3 = q.d;
+        const bool last = tg.re == K - 1;
+        // the halo row below: the next lane, or the next wave's top halo row
+        const V s00 = row_next(e[0]), s01 = row_next(e[1]), s10 = row_next(e[4]), s11 = row_next(e[5]);
+        const V d00 = last ? n0 : s00;
+        const V d01 = last ? n1 : s01;
+        const V d10 = last ? n2 : s10;
+        const V d11 = last ? n3 : s11;
+        // right of the second halo block: core column 0 (left side; on the
+        // right side the outermost halo, where any value will do)
+        const V cR0 = L.col[wv][0][tg.re];
+        const V cR2 = L.col[wv][1][tg.re];
+        const V cDR0 = tg.re + 1 < K ? L.col[wv][0][min(tg.re + 1, 15)] : L.t[wv + 1][0][0].a;
+        h.x0R[0] = e[4]; h.x2R[0] = e[6]; h.x0D[0] = d00; h.x1D[0] = d01; h.x0DR[0] = d10;
+        h.x0R[1] = cR0;  h.x2R[1] = cR2;  h.x0D[1] = d10; h.x1D[1] = d11; h.x0DR[1] = cDR0;
+    }
+    // x0, x2 of the right neighbour of each row's last block (x0 is not
+    // changed by a predict-shaped step, so row r+1's value is also row r's
+    // lower-right operand)
+    V dn[Ly::BX];                                 // the row below the wave
+    fetch_row<BPL>(dn, 0, L.t[wv + 1], lane);
+    V R0[K + 1], R2[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        R0[r] = from_right_or(L.hal[wv][0][r], a[r][0]);
+        R2[r] = from_right_or(L.hal[wv][1][r], a[r][2]);
+    }
+    R0[K] = from_right_or(L.et[wv + 1][1].a, dn[0]);
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        PlusOps<V, BPL> o;
+        if (r + 1 < K) gather_plus<BPL>(a[r], a[r + 1 < K ? r + 1 : r], R0[r], R2[r], R0[r + 1], o);
+        else gather_plus<BPL>(a[r], dn, R0[r], R2[r], R0[r + 1], o);
+        apply_plus<KIND, (1 << BPL) - 1, EDGE, EDGE>(a[r], o, tg.gc, g.gr0 + r, g, c);
+    }
+    apply_plus<KIND, EMASK, EDGE, EDGE>(e, h, tg.ge, tg.gre, g, c);
+}
+
+// Update-shaped step over the tile (after the barrier): core rows bottom to top.
+template <int KIND, int EMASK, bool EDGE, int NW, int BPL, int K, typename V>
+__device__ __forceinline__ void minus_step(V (&a)[K][Lay<BPL>::BX], V (&e)[8], TileLds<V, NW, BPL, K>& L, int lane,
+                                           int wv, const Geo& g, const TileGeo<BPL>& tg, float c) {
+    using Ly = Lay<BPL>;
+    MinusOps<V, 2> h;
+    {
+        const int side = (lane >> 4) & 1;
+        const Vec4<V> q = L.es[wv][side];
+        const V p0 = q.a, p1 = q.b, p2 = q.c, p3 = q.d;
+        // the halo row above: the previous lane, or for the wave's first row
+        // the previous wave's bottom halo row
+        const bool first = tg.re == 0;
+        const V s02 = row_prev(e[2]), s03 = row_prev(e[3]), s12 = row_prev(e[6]), s13 = row_prev(e[7]);
+        const V u02 = first ? p0 : s02;
+        const V u03 = first ? p1 : s03;
+        const V u12 = first ? p2 : s12;
+        const V u13 = first ? p3 : s13;
+        // left of the first halo block: core column 64*BPL - 1 (right side;
+        // on the left side the outermost halo)
+        const V cL1 = L.col[wv][0][tg.re];
+        const V cL3 = L.col[wv][1][tg.re];
+        const V cUL3 = tg.re > 0 ? L.col[wv][1][max(tg.re - 1, 0)] : L.s[wv][Ly::NG - 1][kLanes - 1].d;
+        h.x1l[0] = cL1;  h.x3l[0] = cL3;  h.x2u[0] = u02; h.x3u[0] = u03; h.x3ul[0] = cUL3;
+        h.x1l[1] = e[1]; h.x3l[1] = e[3]; h.x2u[1] = u12; h.x3u[1] = u13; h.x3ul[1] = u03;
+    }
+    // x1, x3 of the left neighbour of each row's first block (x3 is not
+    // changed by an update-shaped step, so row r-1's value is also row r's
+    // upper-left operand); index r + 1 holds row r
+    V up[Ly::BX];                                 // the row above the wave
+    fetch_row<BPL>(up, 2, L.s[wv], lane);
+    V L1[K], L3[K + 1];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        L1[r] = from_left_or(L.hal[wv][0][r], a[r][Ly::LAST + 1]);
+        L3[r + 1] = from_left_or(L.hal[wv][1][r], a[r][Ly::LAST + 3]);
+    }
+    L3[0] = from_left_or(L.es[wv][0].d, up[Ly::LAST + 3]);
 #pragma unroll
     for (int r = K - 1; r >= 0; --r) {
-        MinusOps<V, L::NB> o;
-        if (r > 0) {
-            gather_minus<BPL>(a[r], a[r - 1], from_left_or(a[r - 1][L::E1 + 3], a[r - 1][L::LAST + 3]), o);
-        } else if (wv > 0) {
-            V up[L::BX];
-            fetch_row<BPL>(up, 2, buf[wv - 1], lane);
-            gather_minus<BPL>(a[r], up, from_left_or(up[L::E1 + 3], up[L::LAST + 3]), o);
-        } else {                                  // above the tile: halo
-            gather_minus<BPL>(a[r], a[r], from_left_or(a[r][L::E1 + 3], a[r][L::LAST + 3]), o);
-        }
-        apply_minus<KIND, EMASK, EDGE, EDGE, BPL>(a[r], o, gc, g.gr0 + r, g, c);
+        MinusOps<V, BPL> o;
+        if (r > 0) gather_minus<BPL>(a[r], a[r > 0 ? r - 1 : 0], L1[r], L3[r + 1], L3[r], o);
+        else gather_minus<BPL>(a[r], up, L1[r], L3[r + 1], L3[r], o);
+        apply_minus<KIND, (1 << BPL) - 1, EDGE, EDGE>(a[r], o, tg.gc, g.gr0 + r, g, c);
     }
+    apply_minus<KIND, EMASK, EDGE, EDGE>(e, h, tg.ge, tg.gre, g, c);
 }
 
 // Constant parts of the split (no neighbour access): separable lifting with
 // P0 = c (horizontal, then vertical) and with U0 = c, for every block.
+template <typename V>
+__device__ __forceinline__ void local_predict_block(V* v, float c) {
+    v[1] = fmaf(c, v[0], v[1]);
+    v[3] = fmaf(c, v[2], v[3]);
+    v[2] = fmaf(c, v[0], v[2]);
+    v[3] = fmaf(c, v[1], v[3]);
+}
+template <typename V>
+__device__ __forceinline__ void local_update_block(V* v, float c) {
+    v[0] = fmaf(c, v[1], v[0]);
+    v[2] = fmaf(c, v[3], v[2]);
+    v[0] = fmaf(c, v[2], v[0]);
+    v[1] = fmaf(c, v[3], v[1]);
+}
 template <int K, int BX, typename V>
-__device__ __forceinline__ void local_predict(V (&a)[K][BX], float c) {
+__device__ __forceinline__ void local_predict(V (&a)[K][BX], V (&e)[8], float c) {
 #pragma unroll
     for (int r = 0; r < K; ++r)
 #pragma unroll
-        for (int b = 0; b < BX; b += 4) {
-            a[r][b + 1] = fmaf(c, a[r][b + 0], a[r][b + 1]);
-            a[r][b + 3] = fmaf(c, a[r][b + 2], a[r][b + 3]);
-            a[r][b + 2] = fmaf(c, a[r][b + 0], a[r][b + 2]);
-            a[r][b + 3] = fmaf(c, a[r][b + 1], a[r][b + 3]);
-        }
+        for (int b = 0; b < BX; b += 4) local_predict_block(&a[r][b], c);
+    local_predict_block(&e[0], c);
+    local_predict_block(&e[4], c);
 }
 template <int K, int BX, typename V>
-__device__ __forceinline__ void local_update(V (&a)[K][BX], float c) {
+__device__ __forceinline__ void local_update(V (&a)[K][BX], V (&e)[8], float c) {
 #pragma unroll
     for (int r = 0; r < K; ++r)
 #pragma unroll
-        for (int b = 0; b < BX; b += 4) {
-            a[r][b + 0] = fmaf(c, a[r][b + 1], a[r][b + 0]);
-            a[r][b + 2] = fmaf(c, a[r][b + 3], a[r][b + 2]);
-            a[r][b + 0] = fmaf(c, a[r][b + 2], a[r][b + 0]);
-            a[r][b + 1] = fmaf(c, a[r][b + 3], a[r][b + 1]);
-        }
+        for (int b = 0; b < BX; b += 4) local_update_block(&a[r][b], c);
+    local_update_block(&e[0], c);
+    local_update_block(&e[4], c);
 }
 template <int K, int BX, typename V>
-__device__ __forceinline__ void scale(V (&a)[K][BX], float s0, float s3) {
+__device__ __forceinline__ void scale(V (&a)[K][BX], V (&e)[8], float s0, float s3) {
 #pragma unroll
     for (int r = 0; r < K; ++r)
 #pragma unroll
@@ -488,19 +617,31 @@ __device__ __forceinline__ void scale(V (&a)[K][BX], float s0, float s3) {
             a[r][b + 0] *= s0;
             a[r][b + 3] *= s3;
         }
+    e[0] *= s0; e[3] *= s3; e[4] *= s0; e[7] *= s3;
 }
 
 // The step program of one scale.  Each "sync" is the single barrier of one
-// fused step; the LDS edge row it guards is published just before it.
+// fused step; the LDS rows it guards are published just before it.
 template <int DIR, int WAV, bool EDGE, bool SPLIT, int NW, int BPL, int K, typename V>
-__device__ __forceinline__ void run(V (&a)[K][Lay<BPL>::BX], Vec4<V> (*bT)[Lay<BPL>::NG][kLanes],
-                                    Vec4<V> (*bS)[Lay<BPL>::NG][kLanes], int lane, int wv, const Geo& g,
-                                    const int (&gc)[Lay<BPL>::NB]) {
-#define DWT2_PLUS(KIND_, M_, c_) publish_row<BPL>(a[0], 0, bT[wv], lane); __syncthreads(); \
-    plus_step<KIND_, M_, EDGE, NW, BPL>(a, bT, lane, wv, g, gc, (c_));
-#define DWT2_MINUS(KIND_, M_, c_) publish_row<BPL>(a[K - 1], 2, bS[wv], lane); __syncthreads(); \
-    minus_step<KIND_, M_, EDGE, NW, BPL>(a, bS, lane, wv, g, gc, (c_));
-    // halo masks (E0 = 1, E1 = 2) per step, from the column ranges each stage
+__device__ __forceinline__ void run(V (&a)[K][Lay<BPL>::BX], V (&e)[8], TileLds<V, NW, BPL, K>& L, int lane, int wv,
+                                    const Geo& g, const TileGeo<BPL>& tg) {
+    // the slots no wave publishes to hold zeros (the transposed border
+    // weights multiply values beyond the tile by 0, which must stay finite)
+    if (wv == NW - 1) {
+#pragma unroll
+        for (int q = 0; q < Lay<BPL>::NG; ++q) L.t[NW][q][lane] = Vec4<V>{V(0), V(0), V(0), V(0)};
+        if (lane < 2) L.et[NW][lane] = Vec4<V>{V(0), V(0), V(0), V(0)};
+    }
+    if (wv == 0) {
+#pragma unroll
+        for (int q = 0; q < Lay<BPL>::NG; ++q) L.s[0][q][lane] = Vec4<V>{V(0), V(0), V(0), V(0)};
+        if (lane < 2) L.es[0][lane] = Vec4<V>{V(0), V(0), V(0), V(0)};
+    }
+#define DWT2_PLUS(KIND_, M_, c_) publish_plus<NW, BPL, K>(a, e, L, lane, wv); __syncthreads(); \
+    plus_step<KIND_, M_, EDGE, NW, BPL, K>(a, e, L, lane, wv, g, tg, (c_));
+#define DWT2_MINUS(KIND_, M_, c_) publish_minus<NW, BPL, K>(a, e, L, lane, wv); __syncthreads(); \
+    minus_step<KIND_, M_, EDGE, NW, BPL, K>(a, e, L, lane, wv, g, tg, (c_));
+    // halo masks (first halo block = 1, second = 2) per step, from the column ranges each stage
     // must cover: predict/update/predict/update -> 3, 3, 2, 0;
     // update/predict/update/predict -> 3, 3, 1, 0; predict/update -> 2, 0;
     // update/predict -> 1, 0
@@ -514,10 +655,10 @@ __device__ __forceinline__ void run(V (&a)[K][Lay<BPL>::BX], Vec4<V> (*bT)[Lay<B
         }
     } else if constexpr (DIR == kForward) {
         if constexpr (SPLIT) {
-            local_predict(a, kAlpha);
-            DWT2_PLUS(kSplit, 3, kAlpha) local_update(a, kBeta);
-            DWT2_MINUS(kSplit, 3, kBeta) local_predict(a, kGamma);
-            DWT2_PLUS(kSplit, 2, kGamma) local_update(a, kDelta);
+            local_predict(a, e, kAlpha);
+            DWT2_PLUS(kSplit, 3, kAlpha) local_update(a, e, kBeta);
+            DWT2_MINUS(kSplit, 3, kBeta) local_predict(a, e, kGamma);
+            DWT2_PLUS(kSplit, 2, kGamma) local_update(a, e, kDelta);
             DWT2_MINUS(kSplit, 0, kDelta)
         } else {
             DWT2_PLUS(kFloat, 3, kAlpha)
@@ -525,14 +666,14 @@ __device__ __forceinline__ void run(V (&a)[K][Lay<BPL>::BX], Vec4<V> (*bT)[Lay<B
             DWT2_PLUS(kFloat, 2, kGamma)
             DWT2_MINUS(kFloat, 0, kDelta)
         }
-        scale(a, kZeta2, kZetaM2);
+        scale(a, e, kZeta2, kZetaM2);
     } else if constexpr (DIR == kInverse) {
-        scale(a, kZetaM2, kZeta2);
+        scale(a, e, kZetaM2, kZeta2);
         if constexpr (SPLIT) {
-            DWT2_MINUS(kSplit, 3, -kDelta) local_update(a, -kDelta);
-            DWT2_PLUS(kSplit, 3, -kGamma) local_predict(a, -kGamma);
-            DWT2_MINUS(kSplit, 1, -kBeta) local_update(a, -kBeta);
-            DWT2_PLUS(kSplit, 0, -kAlpha) local_predict(a, -kAlpha);
+            DWT2_MINUS(kSplit, 3, -kDelta) local_update(a, e, -kDelta);
+            DWT2_PLUS(kSplit, 3, -kGamma) local_predict(a, e, -kGamma);
+            DWT2_MINUS(kSplit, 1, -kBeta) local_update(a, e, -kBeta);
+            DWT2_PLUS(kSplit, 0, -kAlpha) local_predict(a, e, -kAlpha);
         } else {
             DWT2_MINUS(kFloat, 3, -kDelta)
             DWT2_PLUS(kFloat, 3, -kGamma)
@@ -542,7 +683,7 @@ __device__ __forceinline__ void run(V (&a)[K][Lay<BPL>::BX], Vec4<V> (*bT)[Lay<B
     } else {
         // W^T = T_1^T S_1^T T_2^T S_2^T Z: transposed steps in reverse order;
         // the transpose of an update is predict-shaped and vice versa.
-        scale(a, kZeta2, kZetaM2);
+        scale(a, e, kZeta2, kZetaM2);
         DWT2_PLUS(kAdj, 3, kDelta)
         DWT2_MINUS(kAdj, 3, kGamma)
         DWT2_PLUS(kAdj, 2, kBeta)
@@ -702,14 +843,16 @@ __device__ __forceinline__ void storeN(T* rowp, int gc, int ncols, bool vec, con
     }
 }
 
-// Load the tile (halo included) into registers.
+// Load the tile into registers: the core rows of the lane (a) and, in the
+// halo lanes, the lane's halo blocks (e).
 template <int DIR, typename T, bool EDGE, int BPL, int K>
-__device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][Lay<BPL>::BX], const LevelParams& P,
-                                          const Geo& g, int gcE0, LaneRole lr) {
+__device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][Lay<BPL>::BX], typename St<T>::V (&e)[8],
+                                          const LevelParams& P, const Geo& g, const TileGeo<BPL>& tg, int lane) {
     using V = typename St<T>::V;
-    using L = Lay<BPL>;
-    const bool vec = P.vec != 0;
-    const bool halo_lane = lr.l0 || lr.l63;
+    const bool vec = EDGE ? P.vec != 0 : true;      // interior tiles run only on aligned images
+    const bool halo_lane = lane < 32 && tg.re < K;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) e[q] = V(0);
     if constexpr (DIR == kForward) {
         const T* in = static_cast<const T*>(P.in);
 #pragma unroll
@@ -722,16 +865,11 @@ __device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][Lay<BPL>::BX
                 load4<T, EDGE>(in, P.in_pitch, row, c, P.h, P.w, vec, b0[0], b0[1], b0[4], b0[5]);
                 load4<T, EDGE>(in, P.in_pitch, row + 1, c, P.h, P.w, vec, b0[2], b0[3], b0[6], b0[7]);
             }
-            if (EDGE) {
-#pragma unroll
-                for (int q = L::E0; q < L::BX; ++q) a[r][q] = V(0);
-            }
-            if (halo_lane) {
-                load4<T, EDGE>(in, P.in_pitch, row, 2 * gcE0, P.h, P.w, vec, a[r][L::E0 + 0], a[r][L::E0 + 1],
-                               a[r][L::E1 + 0], a[r][L::E1 + 1]);
-                load4<T, EDGE>(in, P.in_pitch, row + 1, 2 * gcE0, P.h, P.w, vec, a[r][L::E0 + 2],
-                               a[r][L::E0 + 3], a[r][L::E1 + 2], a[r][L::E1 + 3]);
-            }
+        }
+        if (halo_lane) {
+            const int row = 2 * tg.gre;
+            load4<T, EDGE>(in, P.in_pitch, row, 2 * tg.ge[0], P.h, P.w, vec, e[0], e[1], e[4], e[5]);
+            load4<T, EDGE>(in, P.in_pitch, row + 1, 2 * tg.ge[0], P.h, P.w, vec, e[2], e[3], e[6], e[7]);
         }
     } else {
         const T* ll = static_cast<const T*>(P.in_ll);
@@ -753,18 +891,22 @@ __device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][Lay<BPL>::BX
 #pragma unroll
                 for (int b = 0; b < BPL; ++b) a[r][4 * b + k] = v[b];
             }
-            if (EDGE) {
+        }
+        if (halo_lane) {
+            const int gr = tg.gre;
+            const bool rE = gr >= 0 && gr < g.nEr;
+            const bool rO = gr >= 0 && gr < g.nOr;
+            const int64_t gre = rE ? gr : 0, gro = rO ? gr : 0;
+            const T* rows[4] = {ll + gre * P.in_ll_pitch, det + gre * P.in_pitch + g.nEc,
+                                det + (g.nEr + gro) * P.in_pitch, det + (g.nEr + gro) * P.in_pitch + g.nEc};
+            const int ncols[4] = {g.nEc, g.nOc, g.nEc, g.nOc};
+            const bool ok[4] = {rE, rE, rO, rO};
 #pragma unroll
-                for (int q = L::E0; q < L::BX; ++q) a[r][q] = V(0);
-            }
-            if (halo_lane) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    V v[2];
-                    loadN<T, EDGE, 2>(rows[k], gcE0, ncols[k], ok[k], vec, v);
-                    a[r][L::E0 + k] = v[0];
-                    a[r][L::E1 + k] = v[1];
-                }
+            for (int k = 0; k < 4; ++k) {
+                V v[2];
+                loadN<T, EDGE, 2>(rows[k], tg.ge[0], ncols[k], ok[k], vec, v);
+                e[k] = v[0];
+                e[4 + k] = v[1];
             }
         }
     }
@@ -776,7 +918,7 @@ __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::B
                                            const Geo& g, int wv) {
     using V = typename St<T>::V;
     constexpr int kCoreBY = NW * K - 2 * kHalo;
-    const bool vec = P.vec != 0;
+    const bool vec = EDGE ? P.vec != 0 : true;      // interior tiles run only on aligned images
 #pragma unroll
     for (int r = 0; r < K; ++r) {
         const int tr = wv * K + r;                // row within the tile
@@ -810,18 +952,11 @@ __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::B
     }
 }
 
-// LDS edge buffers of one work-group: one for predict-shaped steps (top rows
-// of the waves), one for update-shaped steps (bottom rows).
-template <typename V, int NW, int BPL> struct TileLds {
-    Vec4<V> t[NW][Lay<BPL>::NG][kLanes];
-    Vec4<V> s[NW][Lay<BPL>::NG][kLanes];
-};
-
 // One tile (tx, ty) of one level: load, the fused steps, store.  The LDS
-// edge buffers belong to the calling work-group.
+// belongs to the calling work-group.
 template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K, int BPL>
 __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
-                                          TileLds<typename St<T>::V, NW, BPL>& lds, int lane, int wv) {
+                                          TileLds<typename St<T>::V, NW, BPL, K>& lds, int lane, int wv) {
     using V = typename St<T>::V;
     using L = Lay<BPL>;
     constexpr int kCoreBY = NW * K - 2 * kHalo;
@@ -829,29 +964,29 @@ __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
     g.nEr = (P.h + 1) >> 1; g.nOr = P.h >> 1;
     g.nEc = (P.w + 1) >> 1; g.nOc = P.w >> 1;
     const int cb0 = tx * L::CORE_BX, rb0 = ty * kCoreBY;
-    LaneRole lr;
-    lr.l0 = lane == 0;
-    lr.l63 = lane == kLanes - 1;
     g.gcL = cb0 + BPL * lane;
     g.gr0 = rb0 - kHalo + wv * K;
-    const int gcE0 = lr.l0 ? cb0 - kHalo : cb0 + L::CORE_BX;
-    int gc[L::NB];
+    TileGeo<BPL> tg;
 #pragma unroll
-    for (int b = 0; b < BPL; ++b) gc[b] = g.gcL + b;
-    gc[BPL] = gcE0;
-    gc[BPL + 1] = gcE0 + 1;
-    // Interior tile: every loaded block has all four components and no
-    // neighbour index of the core's dependency cone needs clamping.
-    const bool interior = rb0 - kHalo >= 0 && cb0 - kHalo >= 0 &&
+    for (int b = 0; b < BPL; ++b) tg.gc[b] = g.gcL + b;
+    tg.re = lane & 15;
+    tg.gre = g.gr0 + tg.re;
+    tg.ge[0] = (lane & 16) ? cb0 + L::CORE_BX : cb0 - kHalo;
+    tg.ge[1] = tg.ge[0] + 1;
+    // Interior tile: every loaded block has all four components, no
+    // neighbour index of the core's dependency cone needs clamping, and (the
+    // image's rows being aligned) every access is a full vector.
+    const bool interior = P.vec && rb0 - kHalo >= 0 && cb0 - kHalo >= 0 &&
                           rb0 + kCoreBY + kHalo <= g.nOr && cb0 + L::CORE_BX + kHalo <= g.nOc;
     V a[K][L::BX];
+    V e[8];
     if (interior) {
-        load_tile<DIR, T, false, BPL>(a, P, g, gcE0, lr);
-        run<DIR, WAV, false, SPLIT, NW, BPL>(a, lds.t, lds.s, lane, wv, g, gc);
+        load_tile<DIR, T, false, BPL>(a, e, P, g, tg, lane);
+        run<DIR, WAV, false, SPLIT, NW, BPL>(a, e, lds, lane, wv, g, tg);
         store_tile<DIR, T, false, NW, BPL>(a, P, g, wv);
     } else {
-        load_tile<DIR, T, true, BPL>(a, P, g, gcE0, lr);
-        run<DIR, WAV, true, false, NW, BPL>(a, lds.t, lds.s, lane, wv, g, gc);
+        load_tile<DIR, T, true, BPL>(a, e, P, g, tg, lane);
+        run<DIR, WAV, true, false, NW, BPL>(a, e, lds, lane, wv, g, tg);
         store_tile<DIR, T, true, NW, BPL>(a, P, g, wv);
     }
 }
@@ -859,7 +994,7 @@ __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
 template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K, int BPL>
 __global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
     using V = typename St<T>::V;
-    __shared__ TileLds<V, NW, BPL> lds;
+    __shared__ TileLds<V, NW, BPL, K> lds;
     const int lane = threadIdx.x & (kLanes - 1);
     // the wave index is uniform: keep it (and every row address) in SGPRs
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
