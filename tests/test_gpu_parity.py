@@ -249,3 +249,49 @@ def test_kernel_configs_bit_identical():
             a0 = d.adj(g, lv, config=0)
             for sh in range(1, d.DWT2_NUM_KERNEL_CONFIGS):
                 assert torch.equal(d.adj(g, lv, config=sh), a0)
+
+
+# ---- every tile configuration against the oracle ---------------------------
+# Shapes with interior tiles for every tile width (subband widths above
+# 2 * (64 * BPL) + 4 blocks) and ragged last tiles: heights leave a partial
+# last wave, widths end one or a few blocks past a tile; (1034, 2062) has odd
+# subband widths (no vector access), (1100, 2104) has subband widths that are
+# multiples of 4 (vector access for both tile widths).
+CFG_SHAPES = [(1100, 2104), (1034, 2062), (2, 3000), (3000, 6)]
+
+
+def tile_configs():
+    return [i for i in range(d.DWT2_NUM_KERNEL_CONFIGS) if d.dwt2_kernel_config(i)[1] == d.DWT2_ALGO_TILE]
+
+
+@pytest.mark.parametrize("shape", CFG_SHAPES)
+def test_tile_configs_against_oracle(shape):
+    h, w = shape
+    x = workloads.uniform(h, w, seed=21)
+    xi = workloads.pixels_u8(h, w, seed=22)
+    lv = min(3, lifting.max_levels(h, w))
+    ref = lifting.fwd(x, "cdf97", lv)
+    ref_i = lifting.fwd(xi, "cdf53", lv)
+    xg, xig = gpu(x), gpu(xi)
+    for cfg in tile_configs():
+        say("tile config vs oracle", cfg, shape, lv)
+        y = d.fwd(xg, "cdf97", lv, config=cfg)
+        assert rel_err(host(y), ref) <= TOL97, cfg
+        assert rel_err(host(d.inv(y, "cdf97", lv, config=cfg)), x) <= TOL97, cfg
+        ys = d.fwd(xg, "cdf97", lv, split=True, config=cfg)
+        assert rel_err(host(ys), ref) <= TOL97, cfg
+        yi = d.fwd(xig, "cdf53", lv, config=cfg)
+        assert np.array_equal(host(yi), ref_i), cfg
+        assert torch.equal(d.inv(yi, "cdf53", lv, config=cfg), xig), cfg
+
+
+@pytest.mark.parametrize("tdt", [torch.bfloat16, torch.float16])
+def test_storage_bound_interior_tiles(tdt):
+    """16-bit storage on an image with interior tiles for every tile width."""
+    h, w, lv = 1100, 2104, 2
+    xs = torch.from_numpy(workloads.uniform(h, w, seed=23)).to(tdt)
+    ref = lifting.fwd(xs.to(torch.float64).numpy(), "cdf97", lv)
+    for cfg in tile_configs():
+        say("storage interior", tdt, cfg)
+        y = d.fwd(xs.to(dev()), "cdf97", lv, config=cfg)
+        assert rel_err(host(y), ref) <= 8 * UNIT[tdt], cfg
