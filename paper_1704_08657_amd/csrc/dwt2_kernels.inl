@@ -912,6 +912,116 @@ __device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][Lay<BPL>::BX
     }
 }
 
+// Whole-point symmetric extension of a sample index p into [0, n), n >= 2:
+// symmetric about both ends, hence periodic with period 2 (n - 1).
+__device__ __forceinline__ int reflect(int p, int n) {
+    if (p >= 0 && p < n) return p;
+    const int period = 2 * (n - 1);
+    int q = p % period;
+    if (q < 0) q += period;
+    return q < n ? q : period - q;
+}
+
+// Border tiles of the forward and inverse transforms: the tile is loaded
+// from the whole-point symmetric extension of the image (forward) or of each
+// subband (inverse: the extension that the forward transform of the extended
+// image has, i.e. each component sample taken at the reflected pixel
+// position), and the fused steps then run without index clamps.  Each step
+// keeps the extension symmetric, and every sum a step forms pairs the same
+// two values as the clamped step at the same place, so every coefficient
+// equals the clamped computation bit for bit.
+template <int DIR, typename T, int BPL, int K>
+__device__ __forceinline__ void load_tile_mirror(typename St<T>::V (&a)[K][Lay<BPL>::BX], typename St<T>::V (&e)[8],
+                                                 const LevelParams& P, const Geo& g, const TileGeo<BPL>& tg,
+                                                 int lane) {
+    using V = typename St<T>::V;
+    const bool vec = P.vec != 0;
+    const bool halo_lane = lane < 32 && tg.re < K;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) e[q] = V(0);
+    if constexpr (DIR == kForward) {
+        const T* in = static_cast<const T*>(P.in);
+        // component k of block (br, bc) of the extended image
+        auto sample = [&](int br, int bc, int k) -> V {
+            const int r = reflect(2 * br + (k >> 1), P.h), c = reflect(2 * bc + (k & 1), P.w);
+            return St<T>::load(in[(int64_t)r * P.in_pitch + c]);
+        };
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const int br = g.gr0 + r;
+#pragma unroll
+            for (int q = 0; q < BPL / 2; ++q) {
+                const int c = 2 * g.gcL + 4 * q;          // first pixel column of blocks 2q, 2q+1
+                V* b0 = &a[r][8 * q];
+                if (vec && c >= 0 && c + 3 < P.w) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int row = reflect(2 * br + h, P.h);
+                        load4<T, false>(in, P.in_pitch, row, c, P.h, P.w, true, b0[2 * h], b0[2 * h + 1],
+                                        b0[4 + 2 * h], b0[4 + 2 * h + 1]);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        b0[k] = sample(br, g.gcL + 2 * q, k);
+                        b0[4 + k] = sample(br, g.gcL + 2 * q + 1, k);
+                    }
+                }
+            }
+        }
+        if (halo_lane) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                e[k] = sample(tg.gre, tg.ge[0], k);
+                e[4 + k] = sample(tg.gre, tg.ge[1], k);
+            }
+        }
+    } else {
+        const T* ll = static_cast<const T*>(P.in_ll);
+        const T* det = static_cast<const T*>(P.in);
+        // row base of subband k (0 LL, 1 HL, 2 LH, 3 HH) at component row br
+        auto row_of = [&](int k, int br) -> const T* {
+            switch (k) {
+                case 0: return ll + (int64_t)br * P.in_ll_pitch;
+                case 1: return det + (int64_t)br * P.in_pitch + g.nEc;
+                case 2: return det + (int64_t)(g.nEr + br) * P.in_pitch;
+                default: return det + (int64_t)(g.nEr + br) * P.in_pitch + g.nEc;
+            }
+        };
+        // component k of block (br, bc) of the extended pyramid level
+        auto sample = [&](int br, int bc, int k) -> V {
+            const int r = (reflect(2 * br + (k >> 1), P.h) - (k >> 1)) >> 1;
+            const int c = (reflect(2 * bc + (k & 1), P.w) - (k & 1)) >> 1;
+            return St<T>::load(row_of(k, r)[c]);
+        };
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const int br = g.gr0 + r;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int ncols = (k & 1) ? g.nOc : g.nEc;
+                if (vec && g.gcL >= 0 && g.gcL + BPL - 1 < ncols) {
+                    const int rr = (reflect(2 * br + (k >> 1), P.h) - (k >> 1)) >> 1;
+                    V v[BPL];
+                    loadN<T, false, BPL>(row_of(k, rr), g.gcL, ncols, true, true, v);
+#pragma unroll
+                    for (int b = 0; b < BPL; ++b) a[r][4 * b + k] = v[b];
+                } else {
+#pragma unroll
+                    for (int b = 0; b < BPL; ++b) a[r][4 * b + k] = sample(br, g.gcL + b, k);
+                }
+            }
+        }
+        if (halo_lane) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                e[k] = sample(tg.gre, tg.ge[0], k);
+                e[4 + k] = sample(tg.gre, tg.ge[1], k);
+            }
+        }
+    }
+}
+
 // Store the core of the tile: the core blocks of every lane, halo rows dropped.
 template <int DIR, typename T, bool EDGE, int NW, int BPL, int K>
 __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::BX], const LevelParams& P,
@@ -984,7 +1094,13 @@ __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
         load_tile<DIR, T, false, BPL>(a, e, P, g, tg, lane);
         run<DIR, WAV, false, SPLIT, NW, BPL>(a, e, lds, lane, wv, g, tg);
         store_tile<DIR, T, false, NW, BPL>(a, P, g, wv);
+    } else if constexpr (DIR != kAdjoint) {
+        // border tile: symmetric extension at load time, unclamped steps
+        load_tile_mirror<DIR, T, BPL>(a, e, P, g, tg, lane);
+        run<DIR, WAV, false, false, NW, BPL>(a, e, lds, lane, wv, g, tg);
+        store_tile<DIR, T, true, NW, BPL>(a, P, g, wv);
     } else {
+        // the adjoint's border weights are not a symmetric extension
         load_tile<DIR, T, true, BPL>(a, e, P, g, tg, lane);
         run<DIR, WAV, true, false, NW, BPL>(a, e, lds, lane, wv, g, tg);
         store_tile<DIR, T, true, NW, BPL>(a, P, g, wv);
