@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--no-forms", action="store_true", help="skip the secondary forms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tune", action="store_true",
+                    help="time every kernel configuration on this GPU first and use the fastest, instead of the "
+                         "committed autotuner cache (tuned_configs.json)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-reference", action="store_true",
                     help="also run a plain 256 MiB device copy (torch copy_) a few times, as the "
@@ -139,9 +142,28 @@ def main():
     ys = [torch.empty_like(xs[0]) for _ in range(pairs)]
     torch.cuda.synchronize()
 
+    from paper_1704_08657_amd import autotune
+
+    # tile shape: the autotuner's committed cache (tuned_configs.json), or
+    # with --tune every kernel configuration timed on this GPU first (untimed,
+    # before the warmup) and the fastest used
+    tuned = {}
+
+    def tune(name, direction, wavelet, dtype, levels, run):
+        if not args.tune:
+            return
+        best, times = autotune.tune_case(direction, wavelet, dtype, N, N, levels, run)
+        tuned[name] = {"config": best, "ms": {str(c): round(t, 5) for c, t in times.items()}}
+
+    tune("headline", "fwd", "cdf97", "f32", 1,
+         lambda c, i: d.fwd(xs[i % pairs], "cdf97", 1, out=ys[i % pairs], config=c))
+
     def fwd_step(i):
         d.fwd(xs[i % pairs], "cdf97", 1, out=ys[i % pairs])
 
+    head_cfg = d.tuned_config("fwd", "cdf97", d.DWT2_F32, N, N, 1)
+    if head_cfg is None:
+        head_cfg = "default"
     total_ms, per = time_steps(torch, fwd_step, args.steps, args.warmup)
     ms_step = total_ms / args.steps
     px = N * N
@@ -151,13 +173,16 @@ def main():
     achieved = abytes / (kern_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "level_kernel<fwd, cdf97, f32>", "algorithmic_bytes_per_launch": abytes,
+                "kernel": f"level_kernel<fwd, cdf97, f32>, kernel configuration {head_cfg}",
+                "algorithmic_bytes_per_launch": abytes,
                 "avg_launch_ms": round(kern_ms, 5), "median_launch_ms": round(float(np.median(per)), 5)}
 
     forms = []
     if not args.no_forms:
-        def form(name, fn, levels, elem, steps=50):
-            tot, pr = time_steps(torch, fn, steps, 5)
+        def form(name, fn, levels, elem, steps=50, tune_key=None):
+            if tune_key is not None:
+                tune(name, *tune_key, levels, lambda c, i: fn(i, c))
+            tot, pr = time_steps(torch, lambda i: fn(i, None), steps, 5)
             ms = float(np.median(pr))
             ab = algorithmic_bytes(N, N, levels, elem)
             forms.append({"form": name, "Gpixel/s": round(px / (ms * 1e-3) / 1e9, 2),
@@ -165,21 +190,29 @@ def main():
                           "hbm_frac": round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
 
         ws5 = d.workspace(N, N, 5, d.DWT2_F32, dev)
-        form("cdf97 fwd f32 5 levels", lambda i: d.fwd(xs[i % pairs], "cdf97", 5, out=ys[i % pairs]), 5, 4)
+        form("cdf97 fwd f32 5 levels", lambda i, c: d.fwd(xs[i % pairs], "cdf97", 5, out=ys[i % pairs], config=c),
+             5, 4, tune_key=("fwd", "cdf97", "f32"))
         form("cdf97 fwd f32 1 level split P0/P1",
-             lambda i: d.fwd(xs[i % pairs], "cdf97", 1, split=True, out=ys[i % pairs]), 1, 4)
-        form("cdf97 inv f32 1 level", lambda i: d.inv(ys[i % pairs], "cdf97", 1, out=xs[i % pairs]), 1, 4)
+             lambda i, c: d.fwd(xs[i % pairs], "cdf97", 1, split=True, out=ys[i % pairs], config=c), 1, 4,
+             tune_key=None)
+        form("cdf97 inv f32 1 level", lambda i, c: d.inv(ys[i % pairs], "cdf97", 1, out=xs[i % pairs], config=c),
+             1, 4, tune_key=("inv", "cdf97", "f32"))
         del ws5
         for tdt, nm in [(torch.bfloat16, "bf16"), (torch.float16, "f16")]:
             xb = [t.to(tdt) for t in xs]
             yb = [torch.empty_like(t) for t in xb]
-            form(f"cdf97 fwd {nm} 1 level", lambda i: d.fwd(xb[i % pairs], "cdf97", 1, out=yb[i % pairs]), 1, 2)
-            form(f"cdf97 fwd {nm} 5 levels", lambda i: d.fwd(xb[i % pairs], "cdf97", 5, out=yb[i % pairs]), 5, 2)
+            form(f"cdf97 fwd {nm} 1 level", lambda i, c: d.fwd(xb[i % pairs], "cdf97", 1, out=yb[i % pairs], config=c),
+                 1, 2, tune_key=("fwd", "cdf97", nm))
+            form(f"cdf97 fwd {nm} 5 levels",
+                 lambda i, c: d.fwd(xb[i % pairs], "cdf97", 5, out=yb[i % pairs], config=c), 5, 2,
+                 tune_key=("fwd", "cdf97", nm))
             del xb, yb
         xi = [(t * 255).to(torch.int32) for t in xs]
         yi = [torch.empty_like(t) for t in xi]
-        form("cdf53 fwd i32 1 level", lambda i: d.fwd(xi[i % pairs], "cdf53", 1, out=yi[i % pairs]), 1, 4)
-        form("cdf53 inv i32 1 level", lambda i: d.inv(yi[i % pairs], "cdf53", 1, out=xi[i % pairs]), 1, 4)
+        form("cdf53 fwd i32 1 level", lambda i, c: d.fwd(xi[i % pairs], "cdf53", 1, out=yi[i % pairs], config=c),
+             1, 4, tune_key=("fwd", "cdf53", "i32"))
+        form("cdf53 inv i32 1 level", lambda i, c: d.inv(yi[i % pairs], "cdf53", 1, out=xi[i % pairs], config=c),
+             1, 4, tune_key=("inv", "cdf53", "i32"))
         del xi, yi
         del xs[1:], ys[1:]
 
@@ -228,13 +261,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"CDF 9/7 forward, 1 level, one {N}x{N} FP32 image, uniform [0,1) seed 0, "
                                "whole-point symmetric borders, non-separable lifting (4 barriers)",
-                   "height": N, "width": N, "levels": 1, "rotating_buffers": pairs},
+                   "height": N, "width": N, "levels": 1, "rotating_buffers": pairs,
+                   "kernel_config": head_cfg},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,
     }
     if copy_ref is not None:
         line["copy_reference"] = copy_ref
+    if tuned:
+        line["autotune"] = tuned
     print(json.dumps(line), flush=True)
 
 

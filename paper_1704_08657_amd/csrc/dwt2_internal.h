@@ -43,7 +43,7 @@ constexpr KernelConfig kConfigs[] = {
     {kAlgoTile, 4, 6, 0, 2},    {kAlgoTile, 8, 2, 0, 4},    {kAlgoStream, 4, 8, 64, 2},
     {kAlgoStream, 1, 8, 64, 2}, {kAlgoStream, 4, 8, 32, 2}};
 constexpr int kNumConfigs = 8;
-constexpr int kDefaultConfig = 3;
+constexpr int kDefaultConfig = 0;
 // Tile kernels deal work over the 8 XCDs in chunks of kRemapRows tile rows
 // (a level) or kBatchChunk tiles (a batched launch); the grid is a multiple
 // of 8 chunks.
