@@ -1022,35 +1022,49 @@ __device__ __forceinline__ void load_tile_mirror(typename St<T>::V (&a)[K][Lay<B
     }
 }
 
-// Store the core of the tile: the core blocks of every lane, halo rows dropped.
+// Store the core of the tile: the core blocks of every lane, halo rows
+// dropped.  Forward, interior tiles of 4-byte samples: one subband after the
+// other (the rows of LL, then HL, LH, HH), which suits the memory system
+// slightly better than interleaving the four quadrants row by row.
 template <int DIR, typename T, bool EDGE, int NW, int BPL, int K>
 __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::BX], const LevelParams& P,
                                            const Geo& g, int wv) {
     using V = typename St<T>::V;
     constexpr int kCoreBY = NW * K - 2 * kHalo;
     const bool vec = EDGE ? P.vec != 0 : true;      // interior tiles run only on aligned images
+    if constexpr (DIR == kForward) {
+        T* ll = static_cast<T*>(P.out_ll);
+        T* det = static_cast<T*>(P.out);
+        constexpr bool kBySubband = !EDGE && sizeof(T) == 4;
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
-        const int tr = wv * K + r;                // row within the tile
-        if (tr < kHalo || tr >= kHalo + kCoreBY) continue;
-        const int gr = g.gr0 + r;
-        if (EDGE && gr >= g.nEr) continue;
-        if constexpr (DIR == kForward) {
-            T* ll = static_cast<T*>(P.out_ll);
-            T* det = static_cast<T*>(P.out);
-            V v[4][BPL];
+        for (int k0 = 0; k0 < (kBySubband ? 4 : 1); ++k0)
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
+            for (int r = 0; r < K; ++r) {
+                const int tr = wv * K + r;        // row within the tile
+                if (tr < kHalo || tr >= kHalo + kCoreBY) continue;
+                const int gr = g.gr0 + r;
+                if (EDGE && gr >= g.nEr) continue;
 #pragma unroll
-                for (int b = 0; b < BPL; ++b) v[k][b] = a[r][4 * b + k];
-            storeN<T, EDGE, BPL>(ll + (int64_t)gr * P.out_ll_pitch, g.gcL, g.nEc, vec, v[0]);
-            storeN<T, EDGE, BPL>(det + (int64_t)gr * P.out_pitch + g.nEc, g.gcL, g.nOc, vec, v[1]);
-            if (!EDGE || gr < g.nOr) {
-                storeN<T, EDGE, BPL>(det + (int64_t)(g.nEr + gr) * P.out_pitch, g.gcL, g.nEc, vec, v[2]);
-                storeN<T, EDGE, BPL>(det + (int64_t)(g.nEr + gr) * P.out_pitch + g.nEc, g.gcL, g.nOc, vec, v[3]);
+                for (int k = (kBySubband ? k0 : 0); k < (kBySubband ? k0 + 1 : 4); ++k) {
+                    if (EDGE && k >= 2 && gr >= g.nOr) continue;
+                    V v[BPL];
+#pragma unroll
+                    for (int b = 0; b < BPL; ++b) v[b] = a[r][4 * b + k];
+                    T* row = k == 0 ? ll + (int64_t)gr * P.out_ll_pitch
+                           : k == 1 ? det + (int64_t)gr * P.out_pitch + g.nEc
+                           : k == 2 ? det + (int64_t)(g.nEr + gr) * P.out_pitch
+                                    : det + (int64_t)(g.nEr + gr) * P.out_pitch + g.nEc;
+                    storeN<T, EDGE, BPL>(row, g.gcL, (k & 1) ? g.nOc : g.nEc, vec, v);
+                }
             }
-        } else {
-            T* img = static_cast<T*>(P.out);
+    } else {
+        T* img = static_cast<T*>(P.out);
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const int tr = wv * K + r;
+            if (tr < kHalo || tr >= kHalo + kCoreBY) continue;
+            const int gr = g.gr0 + r;
+            if (EDGE && gr >= g.nEr) continue;
 #pragma unroll
             for (int q = 0; q < BPL / 2; ++q) {
                 const int c = 2 * g.gcL + 4 * q;
