@@ -11,8 +11,14 @@ Printed: one JSON line with the contract fields, a `roofline` object for the
 level kernel (algorithmic bytes: each pixel read once, each coefficient
 written once = 2 * 4 B/px) and a `cpu_baseline` object (the CPU oracle timed
 on a bounded crop of the same image).  `forms` lists the other forms of the
-path (5 levels, BF16 / FP16 storage, the P0/P1 split, inverse, reversible
-5/3) on the same image size, measured the same way with fewer steps.
+path, measured the same way with fewer steps: 5 levels, the P0/P1 split,
+inverse, BF16 / FP16 storage, reversible 5/3, warm and gradient-input
+variants, 1024^2 (per call and under graph replay), 4096^2 (cold and warm)
+and 16384^2 images, 3 x 8192^2 planes forward + inverse at each storage type
+with coefficient error and reconstruction PSNR, the autograd training step
+(64 x 3 x 1024^2, forward + adjoint backward), and the batched forward
+(eager and graph replay).  `copy_reference` is a plain device copy on the
+same buffers; roofline.of_copy is the headline against it.
 """
 from __future__ import annotations
 
@@ -68,8 +74,7 @@ def parse():
                          "committed autotuner cache (tuned_configs.json)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-reference", action="store_true",
-                    help="also run a plain 256 MiB device copy (torch copy_) a few times, as the "
-                         "known-size reference for hardware byte counters")
+                    help="accepted for older profiling commands; the plain copy always runs")
     return ap.parse_args()
 
 
@@ -175,7 +180,17 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "kernel": f"level_kernel<fwd, cdf97, f32>, kernel configuration {head_cfg}",
                 "algorithmic_bytes_per_launch": abytes,
-                "avg_launch_ms": round(kern_ms, 5), "median_launch_ms": round(float(np.median(per)), 5)}
+                "avg_launch_ms": round(kern_ms, 5), "median_launch_ms": round(float(np.median(per)), 5),
+                "p10_launch_ms": round(float(np.percentile(per, 10)), 5),
+                "p90_launch_ms": round(float(np.percentile(per, 90)), 5)}
+
+    # a plain device copy of one input to one output buffer (N*N*4 bytes read
+    # and written) on the same rotating buffers: the box's streaming bandwidth
+    _, per_c = time_steps(torch, lambda i: ys[i % pairs].copy_(xs[i % pairs]), 20, 3)
+    cms = float(np.median(per_c))
+    copy_ref = {"bytes_per_launch": 2 * N * N * 4, "median_ms": round(cms, 5),
+                "GB/s": round(2 * N * N * 4 / (cms * 1e-3) / 1e9, 1), "kernel": "torch copy_"}
+    roofline["of_copy"] = round(achieved / copy_ref["GB/s"], 4)
 
     forms = []
     if not args.no_forms:
@@ -214,7 +229,123 @@ def main():
         form("cdf53 inv i32 1 level", lambda i, c: d.inv(yi[i % pairs], "cdf53", 1, out=xi[i % pairs], config=c),
              1, 4, tune_key=("inv", "cdf53", "i32"))
         del xi, yi
+        form("cdf97 fwd f32 1 level, warm (one buffer pair, repeated)",
+             lambda i, c: d.fwd(xs[0], "cdf97", 1, out=ys[0], config=c), 1, 4)
+        xg = torch.from_numpy(workloads.gradient_noise(N, N, seed=0)).to(dev)
+        form("cdf97 fwd f32 1 level, gradient + noise input",
+             lambda i, c: d.fwd(xg if i % 2 == 0 else xs[1], "cdf97", 1, out=ys[i % pairs], config=c), 1, 4)
+        del xg
         del xs[1:], ys[1:]
+        torch.cuda.empty_cache()
+
+        def sized_form(name, n, levels, npairs, steps=40, graph_calls=0):
+            """Forward CDF 9/7 FP32 on n x n images rotating over npairs
+            input/output pairs (cold when they total >= 1 GiB; warm with one
+            pair).  graph_calls > 0: also time one captured graph replaying
+            that many calls (per-call time = replay time / graph_calls)."""
+            g = torch.Generator(device=dev).manual_seed(7)
+            xn = [torch.rand((n, n), device=dev, generator=g) for _ in range(npairs)]
+            yn = [torch.empty_like(t) for t in xn]
+            def run(i):
+                d.fwd(xn[i % npairs], "cdf97", levels, out=yn[i % npairs])
+            _, pr = time_steps(torch, run, steps, 5)
+            ms = float(np.median(pr))
+            ab = algorithmic_bytes(n, n, levels, 4)
+            entry = {"form": name, "Gpixel/s": round(n * n / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 5),
+                     "GB/s": round(ab / (ms * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "buffer_pairs": npairs, "pairs_GiB": round(2 * npairs * n * n * 4 / 2 ** 30, 3)}
+            if graph_calls:
+                s2 = torch.cuda.Stream()
+                s2.wait_stream(torch.cuda.current_stream())
+                with torch.cuda.stream(s2):
+                    for i in range(graph_calls):
+                        run(i)
+                torch.cuda.current_stream().wait_stream(s2)
+                torch.cuda.synchronize()
+                gr = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(gr, stream=s2):
+                    for i in range(graph_calls):
+                        run(i)
+                _, pg = time_steps(torch, lambda i: gr.replay(), 20, 3)
+                gms = float(np.median(pg)) / graph_calls
+                entry.update({"graph_calls": graph_calls, "graph_ms_per_call": round(gms, 5),
+                              "graph_Gpixel/s": round(n * n / (gms * 1e-3) / 1e9, 2)})
+                del gr
+            forms.append(entry)
+            del xn, yn
+            torch.cuda.empty_cache()
+
+        sized_form("cdf97 fwd f32 1 level, 4096^2 cold", 4096, 1, 8)
+        sized_form("cdf97 fwd f32 1 level, 4096^2 warm", 4096, 1, 1)
+        sized_form("cdf97 fwd f32 5 levels, 4096^2 cold", 4096, 5, 8)
+        sized_form("cdf97 fwd f32 1 level, 1024^2 cold, per call and under graph replay", 1024, 1, 64,
+                   graph_calls=64)
+        sized_form("cdf97 fwd f32 1 level, 16384^2", 16384, 1, 2, steps=20)
+        sized_form("cdf97 fwd f32 5 levels, 16384^2", 16384, 5, 2, steps=20)
+
+        # precision: 3 x 8192^2 planes (seed 3), 5-level forward + inverse per
+        # step, FP32 / BF16 / FP16 storage.  Errors of the 16-bit forms are
+        # taken against the FP32-storage transform of the same rounded input
+        # (which the parity tests hold within 1e-5 of the FP64 oracle) and,
+        # for the reconstruction, against the rounded input and the FP32
+        # original (PSNR with peak 1.0).
+        x3 = torch.from_numpy(workloads.planes(3, N, N, seed=3)).to(dev)
+        c32 = None
+        for tdt, nm in [(torch.float32, "f32"), (torch.bfloat16, "bf16"), (torch.float16, "f16")]:
+            xq = x3.to(tdt)
+            cq = torch.empty_like(xq)
+            rq = torch.empty_like(xq)
+
+            def fwd_inv(i, xq=xq, cq=cq, rq=rq):
+                d.fwd(xq, "cdf97", 5, out=cq)
+                d.inv(cq, "cdf97", 5, out=rq)
+            _, pr = time_steps(torch, fwd_inv, 10, 2)
+            ms = float(np.median(pr))
+            el = 4 if tdt == torch.float32 else 2
+            ab = 2 * 3 * algorithmic_bytes(N, N, 5, el)
+            entry = {"form": f"cdf97 fwd+inv {nm} 5 levels, 3 x {N}^2 planes",
+                     "Gpixel/s": round(3 * N * N / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
+                     "GB/s": round(ab / (ms * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            fwd_inv(0)
+            torch.cuda.synchronize()
+            ref = d.fwd(xq.float(), "cdf97", 5)
+            if tdt == torch.float32:
+                c32 = ref
+            err = (cq.float() - ref).abs().max().item()
+            entry["coeff_max_abs_vs_fp32_storage"] = err
+            entry["coeff_max_abs_rel"] = err / ref.abs().max().item()
+            for tag, base in (("rounded_input", xq.float()), ("fp32_original", x3)):
+                mse = ((rq.float() - base) ** 2).mean().item()
+                entry[f"psnr_db_vs_{tag}"] = round(10 * np.log10(1.0 / mse), 2) if mse > 0 else None
+            forms.append(entry)
+            del xq, cq, rq, ref
+            torch.cuda.empty_cache()
+        del x3, c32
+        torch.cuda.empty_cache()
+
+        # differentiation: 64 x 3 x 1024^2 FP32 (seed 4), 3-level forward via
+        # the autograd function, loss = sum |details| + MSE(LL_3, target (seed
+        # 5)), backward through the hand-written adjoint
+        xa = torch.from_numpy(workloads.planes(64 * 3, 1024, 1024, seed=4).reshape(64, 3, 1024, 1024)).to(dev)
+        xa.requires_grad_(True)
+        tgt = torch.from_numpy(workloads.planes(64 * 3, 128, 128, seed=5).reshape(64, 3, 128, 128)).to(dev)
+
+        def train_step(i):
+            y = d.dwt2(xa, 3)
+            ll = y[..., :128, :128]
+            loss = y.abs().sum() - ll.abs().sum() + ((ll - tgt) ** 2).mean()
+            loss.backward()
+            xa.grad = None
+        _, pr = time_steps(torch, train_step, 10, 2)
+        ms = float(np.median(pr))
+        ab = 2 * 64 * 3 * algorithmic_bytes(1024, 1024, 3, 4)
+        forms.append({"form": "autograd: 64 x 3 x 1024^2 FP32, 3-level forward + loss + adjoint backward",
+                      "Gpixel/s": round(64 * 3 * 1024 * 1024 / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
+                      "transform_GB/s": round(ab / (ms * 1e-3) / 1e9, 1)})
+        del xa, tgt
+        torch.cuda.empty_cache()
 
         # batched, a planner launch plus one launch per level: 256 images with H, W uniform in [64, 4096] (even), 5 levels
         def batched_form(name, shapes, seed, steps=5):
@@ -223,26 +354,44 @@ def main():
             call = d.BatchedForward(imgs, 5)
             _, pr = time_steps(torch, lambda i: call.run(), steps, 2)
             ms = float(np.median(pr))
+            # the same call captured once in a graph and replayed
+            s2 = torch.cuda.Stream()
+            s2.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s2):
+                call.run()
+            torch.cuda.current_stream().wait_stream(s2)
+            torch.cuda.synchronize()
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr, stream=s2):
+                call.run()
+            _, pg = time_steps(torch, lambda i: gr.replay(), steps, 2)
+            gms = float(np.median(pg))
             npx = sum(h * w for h, w in shapes)
             ab = sum(algorithmic_bytes(h, w, 5, 4) for h, w in shapes)
             forms.append({"form": name, "Gpixel/s": round(npx / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
                           "GB/s": round(ab / (ms * 1e-3) / 1e9, 1),
                           "hbm_frac": round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "graph_Gpixel/s": round(npx / (gms * 1e-3) / 1e9, 2), "graph_ms": round(gms, 4),
                           "images": len(shapes), "pixels": npx})
-            del imgs, call
+            del imgs, call, gr
             torch.cuda.empty_cache()
 
         batched_form("cdf97 fwd f32 5 levels, batched: 256 uneven images 64..4096",
                      workloads.uneven_shapes(256, 64, 4096, seed=1), seed=1)
         batched_form("cdf97 fwd f32 5 levels, batched: 1024 images 256x256", [(256, 256)] * 1024, seed=2, steps=10)
 
-    copy_ref = None
-    if args.copy_reference:
-        # a plain copy of one input to one output buffer: reads and writes N*N*4 bytes
-        _, per_c = time_steps(torch, lambda i: ys[i % pairs].copy_(xs[i % pairs]), 10, 2)
-        cms = float(np.median(per_c))
-        copy_ref = {"bytes_per_launch": 2 * N * N * 4, "median_ms": round(cms, 5),
-                    "GB/s": round(2 * N * N * 4 / (cms * 1e-3) / 1e9, 1)}
+        # the same 1024 equal-size images as one plane batch (one launch per level)
+        xp = torch.rand((1024, 256, 256), device=dev, generator=torch.Generator(device=dev).manual_seed(2))
+        yp = torch.empty_like(xp)
+        _, pr = time_steps(torch, lambda i: d.fwd(xp, "cdf97", 5, out=yp), 10, 2)
+        ms = float(np.median(pr))
+        ab = 1024 * algorithmic_bytes(256, 256, 5, 4)
+        forms.append({"form": "cdf97 fwd f32 5 levels, plane batch: 1024 images 256x256",
+                      "Gpixel/s": round(1024 * 256 * 256 / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
+                      "GB/s": round(ab / (ms * 1e-3) / 1e9, 1),
+                      "hbm_frac": round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+        del xp, yp
+
 
     cpu = None if args.no_cpu else cpu_baseline(x_host, args.cpu_seconds)
 
@@ -267,8 +416,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
     }
-    if copy_ref is not None:
-        line["copy_reference"] = copy_ref
+    line["copy_reference"] = copy_ref
     if tuned:
         line["autotune"] = tuned
     print(json.dumps(line), flush=True)

@@ -67,7 +67,7 @@ typedef enum {
     DWT2_E_ALIAS = -9,      /* src, dst or workspace overlap                    */
     DWT2_E_HIP = -10,       /* HIP runtime error at launch                      */
     DWT2_E_FLAGS = -11,     /* unknown flag, or flag not valid for the wavelet  */
-    DWT2_E_COUNT = -12      /* batched call: count < 1                          */
+    DWT2_E_COUNT = -12      /* batched call: count < 1; plane batch: planes < 1 */
 } dwt2_status;
 
 typedef enum {
@@ -154,6 +154,33 @@ int dwt2_adj(const void* src, void* dst, int32_t height, int32_t width,
              dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,
              unsigned flags, void* workspace, size_t workspace_bytes,
              void* stream);
+
+/* Plane batches (channels, batch items): `planes` images of the same shape
+ * and pitch whose origins lie `src_plane_stride` / `dst_plane_stride`
+ * elements apart, transformed as dwt2_fwd / dwt2_inv / dwt2_adj would
+ * transform each one (bit-identical results), with one launch per level for
+ * all planes.  planes >= 1 (else DWT2_E_COUNT); with planes > 1 each stride
+ * must cover a whole plane, (height - 1) * pitch + width elements (else
+ * DWT2_E_PITCH); no plane of src may overlap any of dst or the workspace.
+ * The workspace holds the intermediate LL bands of every plane:
+ * dwt2_workspace_bytes_planes, which returns a dwt2_status. */
+int dwt2_workspace_bytes_planes(int32_t height, int32_t width, int levels, dwt2_dtype dtype,
+                                int32_t planes, size_t* bytes);
+int dwt2_fwd_planes(const void* src, void* dst, int32_t planes, int64_t src_plane_stride,
+                    int64_t dst_plane_stride, int32_t height, int32_t width, int64_t src_pitch,
+                    int64_t dst_pitch, dwt2_dtype dtype, dwt2_wavelet wavelet, int levels,
+                    dwt2_boundary boundary, unsigned flags, void* workspace,
+                    size_t workspace_bytes, void* stream);
+int dwt2_inv_planes(const void* src, void* dst, int32_t planes, int64_t src_plane_stride,
+                    int64_t dst_plane_stride, int32_t height, int32_t width, int64_t src_pitch,
+                    int64_t dst_pitch, dwt2_dtype dtype, dwt2_wavelet wavelet, int levels,
+                    dwt2_boundary boundary, unsigned flags, void* workspace,
+                    size_t workspace_bytes, void* stream);
+int dwt2_adj_planes(const void* src, void* dst, int32_t planes, int64_t src_plane_stride,
+                    int64_t dst_plane_stride, int32_t height, int32_t width, int64_t src_pitch,
+                    int64_t dst_pitch, dwt2_dtype dtype, dwt2_wavelet wavelet, int levels,
+                    dwt2_boundary boundary, unsigned flags, void* workspace,
+                    size_t workspace_bytes, void* stream);
 
 /* Describe kernel configuration `index` (0 .. DWT2_NUM_KERNEL_CONFIGS-1):
  * algorithm (DWT2_ALGO_*), wave64s per work-group, block rows per lane

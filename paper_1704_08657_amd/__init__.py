@@ -43,12 +43,18 @@ _c_int, _c_i32, _c_i64, _c_u, _c_sz, _c_p = (ctypes.c_int, ctypes.c_int32, ctype
                                              ctypes.c_uint, ctypes.c_size_t, ctypes.c_void_p)
 _TRANSFORM_ARGS = [_c_p, _c_p, _c_i32, _c_i32, _c_i64, _c_i64, _c_int, _c_int, _c_int, _c_int,
                    _c_u, _c_p, _c_sz, _c_p]
+_PLANES_ARGS = [_c_p, _c_p, _c_i32, _c_i64, _c_i64, _c_i32, _c_i32, _c_i64, _c_i64, _c_int, _c_int, _c_int,
+                _c_int, _c_u, _c_p, _c_sz, _c_p]
 SIGNATURES = {
     "dwt2_max_levels": (_c_int, [_c_i32, _c_i32]),
     "dwt2_workspace_bytes": (_c_int, [_c_i32, _c_i32, _c_int, _c_int, ctypes.POINTER(_c_sz)]),
     "dwt2_fwd": (_c_int, _TRANSFORM_ARGS),
     "dwt2_inv": (_c_int, _TRANSFORM_ARGS),
     "dwt2_adj": (_c_int, _TRANSFORM_ARGS),
+    "dwt2_workspace_bytes_planes": (_c_int, [_c_i32, _c_i32, _c_int, _c_int, _c_i32, ctypes.POINTER(_c_sz)]),
+    "dwt2_fwd_planes": (_c_int, _PLANES_ARGS),
+    "dwt2_inv_planes": (_c_int, _PLANES_ARGS),
+    "dwt2_adj_planes": (_c_int, _PLANES_ARGS),
     "dwt2_kernel_config": (_c_int, [_c_int] + [ctypes.POINTER(_c_int)] * 5),
     "dwt2_workspace_bytes_batched": (_c_int, [_c_p, _c_int, _c_int, _c_int, ctypes.POINTER(_c_sz)]),
     "dwt2_fwd_batched": (_c_int, [_c_p, _c_p, _c_int, _c_int, _c_int, _c_int, _c_int, _c_u, _c_p, _c_sz, _c_p]),
@@ -149,12 +155,14 @@ def _stream_ptr(x):
     return ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
 
 
-def workspace(h: int, w: int, levels: int, dtype, device):
-    """A workspace tensor for one call on an h x w image (None if not needed)."""
+def workspace(h: int, w: int, levels: int, dtype, device, planes: int = 1):
+    """A workspace tensor for one call on `planes` h x w images (None if not needed)."""
     torch = _torch()
-    st, n = dwt2_workspace_bytes(h, w, levels, dtype)
+    n = ctypes.c_size_t(0)
+    st = lib().dwt2_workspace_bytes_planes(h, w, levels, dtype, planes, ctypes.byref(n))
+    n = n.value
     if st != DWT2_OK:
-        raise DWT2Error(st, "dwt2_workspace_bytes")
+        raise DWT2Error(st, "dwt2_workspace_bytes_planes")
     if n == 0:
         return None
     return torch.empty(n, dtype=torch.uint8, device=device)
@@ -180,41 +188,48 @@ def _transform(fn, name, x, wavelet, levels, split, out, config=None):
         _check(out)
         if out.shape != x.shape or out.dtype != x.dtype:
             raise ValueError("out must match the input's shape and dtype")
+        if not out.is_contiguous():
+            raise ValueError("out must be contiguous")
         out = out.reshape(x2.shape)
     H, W = x2.shape[-2:]
+    planes = x2.shape[0]
     dt = dtype_code(x2)
-    ws = workspace(H, W, levels, dt, x2.device)
-    ws_ptr = ctypes.c_void_p(ws.data_ptr() if ws is not None else 0)
-    ws_n = ws.numel() if ws is not None else 0
     stream = _stream_ptr(x2)
     flags = DWT2_FLAG_SPLIT if split else 0
     if config is None:
         config = tuned_config(_DIRECTIONS[name], wavelet, dt, H, W, levels)
     if config is not None:
         flags |= DWT2_FLAG_KERNEL(config)
-    for i in range(x2.shape[0]):
-        st = fn(ctypes.c_void_p(x2[i].data_ptr()), ctypes.c_void_p(out[i].data_ptr()), H, W,
-                x2.stride(-2), out.stride(-2), dt, WAVELETS[wavelet], levels,
-                DWT2_SYMMETRIC_WHOLE, flags, ws_ptr, ws_n, stream)
+    # one call for all planes (at most 2^31 - 1 per call)
+    step = (1 << 31) - 1
+    for p0 in range(0, planes, step):
+        n = min(step, planes - p0)
+        ws = workspace(H, W, levels, dt, x2.device, n)
+        ws_ptr = ctypes.c_void_p(ws.data_ptr() if ws is not None else 0)
+        ws_n = ws.numel() if ws is not None else 0
+        st = fn(ctypes.c_void_p(x2[p0].data_ptr()), ctypes.c_void_p(out[p0].data_ptr()), n,
+                x2.stride(0), out.stride(0), H, W, x2.stride(-2), out.stride(-2), dt, WAVELETS[wavelet],
+                levels, DWT2_SYMMETRIC_WHOLE, flags, ws_ptr, ws_n, stream)
         if st != DWT2_OK:
             raise DWT2Error(st, name)
     return out.reshape(x.shape)
 
 
 def fwd(x, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None):
-    """Forward transform of every [H, W] plane of x into a Mallat pyramid.
-    `config` selects a kernel configuration index (None: library default)."""
-    return _transform(dwt2_fwd, "dwt2_fwd", x, wavelet, levels, split, out, config)
+    """Forward transform of every [H, W] plane of x into a Mallat pyramid
+    (all planes in one call: one launch per level).  `config` selects a
+    kernel configuration index (None: tuned or library default)."""
+    return _transform(lib().dwt2_fwd_planes, "dwt2_fwd", x, wavelet, levels, split, out, config)
 
 
 def inv(c, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None):
     """Inverse transform of every [H, W] Mallat pyramid of c."""
-    return _transform(dwt2_inv, "dwt2_inv", c, wavelet, levels, split, out, config)
+    return _transform(lib().dwt2_inv_planes, "dwt2_inv", c, wavelet, levels, split, out, config)
 
 
 def adj(g, levels: int = 1, out=None, config=None):
     """Adjoint W^T g of the CDF 9/7 forward transform (cotangent in Mallat layout)."""
-    return _transform(dwt2_adj, "dwt2_adj", g, "cdf97", levels, False, out, config)
+    return _transform(lib().dwt2_adj_planes, "dwt2_adj", g, "cdf97", levels, False, out, config)
 
 
 class dwt2_image(ctypes.Structure):

@@ -61,18 +61,29 @@ void plan_levels(int32_t h, int32_t w, int levels, Plan* p) {
     }
 }
 
-// Two ping-pong buffers for intermediate LL bands: buffer A holds the LL of
-// levels 1, 3, 5, ... (largest: level 1), buffer B of levels 2, 4, ...
-void ws_layout(const Plan& p, size_t es, size_t* off_b, size_t* total) {
+// Two ping-pong buffers per plane for intermediate LL bands: buffer A holds
+// the LL of levels 1, 3, 5, ... (largest: level 1), buffer B of levels 2,
+// 4, ...  All planes' A buffers come first (plane stride a), then all B
+// buffers (plane stride b); a and b are multiples of kWsAlign bytes.
+struct WsLayout {
+    size_t a, b;        // bytes of one plane's buffer A / B
+    size_t off_b;       // offset of the B region
+    size_t total;
+};
+
+WsLayout ws_layout(const Plan& p, size_t es, int32_t planes) {
     size_t a = 0, b = 0;
     for (int l = 0; l + 1 < p.levels; ++l) {  // LL of level l+1 (0-based l) is kept
         const int32_t he = (p.h[l] + 1) / 2, we = (p.w[l] + 1) / 2;
         const size_t sz = (size_t)he * (size_t)ws_pitch(we) * es;
         if (l % 2 == 0) a = a > sz ? a : sz; else b = b > sz ? b : sz;
     }
-    a = (a + kWsAlign - 1) / kWsAlign * kWsAlign;
-    *off_b = a;
-    *total = a + b;
+    WsLayout L;
+    L.a = (a + kWsAlign - 1) / kWsAlign * kWsAlign;
+    L.b = (b + kWsAlign - 1) / kWsAlign * kWsAlign;
+    L.off_b = L.a * (size_t)planes;
+    L.total = L.off_b + L.b * (size_t)planes;
+    return L;
 }
 
 bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
@@ -85,10 +96,16 @@ size_t span_bytes(int32_t h, int32_t w, int64_t pitch, size_t es) {
     return ((size_t)(h - 1) * (size_t)pitch + (size_t)w) * es;
 }
 
-int validate(const void* src, void* dst, int32_t h, int32_t w, int64_t sp, int64_t dp,
-             int dtype, int wavelet, int levels, int boundary, unsigned flags,
+// Bytes from the first to the last element of `planes` planes.
+size_t planes_span_bytes(int32_t planes, int64_t plane_stride, int32_t h, int32_t w, int64_t pitch, size_t es) {
+    return (size_t)(planes - 1) * (size_t)plane_stride * es + span_bytes(h, w, pitch, es);
+}
+
+int validate(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dps, int32_t h, int32_t w,
+             int64_t sp, int64_t dp, int dtype, int wavelet, int levels, int boundary, unsigned flags,
              const void* ws, size_t ws_bytes, bool adjoint) {
     if (!src || !dst) return DWT2_E_NULL;
+    if (planes < 1) return DWT2_E_COUNT;
     if (wavelet != DWT2_CDF97 && wavelet != DWT2_CDF53_REV) return DWT2_E_WAVELET;
     if (dtype != DWT2_F32 && dtype != DWT2_BF16 && dtype != DWT2_F16 && dtype != DWT2_I32)
         return DWT2_E_DTYPE;
@@ -101,12 +118,15 @@ int validate(const void* src, void* dst, int32_t h, int32_t w, int64_t sp, int64
     if (adjoint && wavelet != DWT2_CDF97) return DWT2_E_WAVELET;
     if (h < 2 || w < 2 || h > kMaxSide || w > kMaxSide) return DWT2_E_SHAPE;
     if (sp < w || dp < w) return DWT2_E_PITCH;
+    // planes of one buffer must not overlap
+    const int64_t plane_elems = (int64_t)(h - 1) * sp + w, plane_elems_d = (int64_t)(h - 1) * dp + w;
+    if (planes > 1 && (sps < plane_elems || dps < plane_elems_d)) return DWT2_E_PITCH;
     if (levels < 1 || levels > max_levels(h, w)) return DWT2_E_LEVELS;
     size_t need = 0;
-    dwt2_workspace_bytes(h, w, levels, (dwt2_dtype)dtype, &need);
+    dwt2_workspace_bytes_planes(h, w, levels, (dwt2_dtype)dtype, planes, &need);
     if (need > 0 && (!ws || ws_bytes < need)) return DWT2_E_WORKSPACE;
     const size_t es = elem_size(dtype);
-    const size_t ns = span_bytes(h, w, sp, es), nd = span_bytes(h, w, dp, es);
+    const size_t ns = planes_span_bytes(planes, sps, h, w, sp, es), nd = planes_span_bytes(planes, dps, h, w, dp, es);
     if (ranges_overlap(src, ns, dst, nd)) return DWT2_E_ALIAS;
     if (need > 0 && (ranges_overlap(ws, need, src, ns) || ranges_overlap(ws, need, dst, nd)))
         return DWT2_E_ALIAS;
@@ -148,42 +168,71 @@ int config_of(unsigned flags) {
     return t == 0 ? dwt2::kDefaultConfig : (int)t - 1;
 }
 
+// Launch one level for every plane, in grid chunks of at most
+// kMaxGridPlanes planes.
+int launch_planes(dwt2::Direction dir, int wavelet, int dtype, unsigned flags, dwt2::LevelParams lp,
+                  int32_t planes, size_t es, hipStream_t s) {
+    for (int32_t p0 = 0; p0 < planes; p0 += dwt2::kMaxGridPlanes) {
+        const int32_t n = planes - p0 < dwt2::kMaxGridPlanes ? planes - p0 : dwt2::kMaxGridPlanes;
+        dwt2::LevelParams q = lp;
+        if (p0 > 0) {
+            q.in = lp.in ? (const char*)lp.in + (size_t)p0 * (size_t)lp.in_ps * es : nullptr;
+            q.in_ll = lp.in_ll ? (const char*)lp.in_ll + (size_t)p0 * (size_t)lp.in_ll_ps * es : nullptr;
+            q.out = lp.out ? (char*)lp.out + (size_t)p0 * (size_t)lp.out_ps * es : nullptr;
+            q.out_ll = lp.out_ll ? (char*)lp.out_ll + (size_t)p0 * (size_t)lp.out_ll_ps * es : nullptr;
+        }
+        const int rc = report(dwt2::launch_level(dir, to_wav(wavelet), to_dtype(dtype),
+                                                 (flags & DWT2_FLAG_SPLIT) != 0, config_of(flags), q, n, s));
+        if (rc) return rc;
+    }
+    return DWT2_OK;
+}
+
+// Vector access needs every plane's row bases aligned: the plane strides
+// (unused when there is one plane) as well as the pitches.
+bool stride_ok(int32_t planes, int64_t stride, int v) { return planes == 1 || stride % v == 0; }
+
 // Forward: level l reads the LL of level l-1 (src for l = 0) and writes its
 // details into dst at the level's region origin (dst itself: every level's
 // region starts at (0, 0)), its LL into the workspace or, for the last level,
 // into dst.
-int run_forward(const void* src, void* dst, int32_t h, int32_t w, int64_t sp, int64_t dp,
-                int dtype, int wavelet, int levels, unsigned flags, void* ws, hipStream_t s) {
+int run_forward(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dps, int32_t h, int32_t w,
+                int64_t sp, int64_t dp, int dtype, int wavelet, int levels, unsigned flags, void* ws,
+                hipStream_t s) {
     Plan p;
     plan_levels(h, w, levels, &p);
     const size_t es = elem_size(dtype);
-    size_t off_b = 0, total = 0;
-    ws_layout(p, es, &off_b, &total);
-    char* bufs[2] = {(char*)ws, (char*)ws + off_b};
+    const WsLayout L = ws_layout(p, es, planes);
+    char* bufs[2] = {(char*)ws, (char*)ws + L.off_b};
+    const int64_t buf_ps[2] = {(int64_t)(L.a / es), (int64_t)(L.b / es)};
     const void* in = src;
-    int64_t in_pitch = sp;
+    int64_t in_pitch = sp, in_ps = sps;
     for (int l = 0; l < levels; ++l) {
         dwt2::LevelParams lp{};
         lp.h = p.h[l];
         lp.w = p.w[l];
         lp.in = in;
         lp.in_pitch = in_pitch;
+        lp.in_ps = in_ps;
         lp.out = dst;
         lp.out_pitch = dp;
+        lp.out_ps = dps;
         const bool last = l + 1 == levels;
         lp.out_ll = last ? dst : (void*)bufs[l % 2];
         lp.out_ll_pitch = last ? dp : ws_pitch((lp.w + 1) / 2);
+        lp.out_ll_ps = last ? dps : buf_ps[l % 2];
         plan_grid(config_of(flags), &lp);
         const int32_t nEc = (lp.w + 1) / 2;
         const int sv = dwt2::subband_vec(dwt2::kConfigs[config_of(flags)]);
-        lp.vec = aligned(lp.in, 4 * es) && lp.in_pitch % 4 == 0 &&
-                 aligned(lp.out, sv * es) && lp.out_pitch % sv == 0 && nEc % sv == 0 &&
-                 aligned(lp.out_ll, sv * es) && lp.out_ll_pitch % sv == 0;
-        const int rc = report(dwt2::launch_level(dwt2::kForward, to_wav(wavelet), to_dtype(dtype),
-                                                 (flags & DWT2_FLAG_SPLIT) != 0, config_of(flags), lp, s));
+        lp.vec = aligned(lp.in, 4 * es) && lp.in_pitch % 4 == 0 && stride_ok(planes, lp.in_ps, 4) &&
+                 aligned(lp.out, sv * es) && lp.out_pitch % sv == 0 && stride_ok(planes, lp.out_ps, sv) &&
+                 nEc % sv == 0 && aligned(lp.out_ll, sv * es) && lp.out_ll_pitch % sv == 0 &&
+                 stride_ok(planes, lp.out_ll_ps, sv);
+        const int rc = launch_planes(dwt2::kForward, wavelet, dtype, flags, lp, planes, es, s);
         if (rc) return rc;
         in = lp.out_ll;
         in_pitch = lp.out_ll_pitch;
+        in_ps = lp.out_ll_ps;
     }
     return DWT2_OK;
 }
@@ -191,39 +240,43 @@ int run_forward(const void* src, void* dst, int32_t h, int32_t w, int64_t sp, in
 // Inverse / adjoint: coarsest level first.  Level l reads its LL (src for the
 // coarsest level, else the workspace written by level l+1) and its details
 // from src, and writes its image into the workspace or, for l = 0, into dst.
-int run_backward(dwt2::Direction dir, const void* src, void* dst, int32_t h, int32_t w,
-                 int64_t sp, int64_t dp, int dtype, int wavelet, int levels, unsigned flags,
-                 void* ws, hipStream_t s) {
+int run_backward(dwt2::Direction dir, const void* src, void* dst, int32_t planes, int64_t sps, int64_t dps,
+                 int32_t h, int32_t w, int64_t sp, int64_t dp, int dtype, int wavelet, int levels,
+                 unsigned flags, void* ws, hipStream_t s) {
     Plan p;
     plan_levels(h, w, levels, &p);
     const size_t es = elem_size(dtype);
-    size_t off_b = 0, total = 0;
-    ws_layout(p, es, &off_b, &total);
-    char* bufs[2] = {(char*)ws, (char*)ws + off_b};
+    const WsLayout L = ws_layout(p, es, planes);
+    char* bufs[2] = {(char*)ws, (char*)ws + L.off_b};
+    const int64_t buf_ps[2] = {(int64_t)(L.a / es), (int64_t)(L.b / es)};
     const void* ll = src;
-    int64_t ll_pitch = sp;
+    int64_t ll_pitch = sp, ll_ps = sps;
     for (int l = levels - 1; l >= 0; --l) {
         dwt2::LevelParams lp{};
         lp.h = p.h[l];
         lp.w = p.w[l];
         lp.in = src;
         lp.in_pitch = sp;
+        lp.in_ps = sps;
         lp.in_ll = ll;
         lp.in_ll_pitch = ll_pitch;
+        lp.in_ll_ps = ll_ps;
         // the image of level l is the LL of level l-1 (kept in buffer (l-1) % 2)
         lp.out = l == 0 ? dst : (void*)bufs[(l - 1) % 2];
         lp.out_pitch = l == 0 ? dp : ws_pitch(lp.w);
+        lp.out_ps = l == 0 ? dps : buf_ps[(l - 1) % 2];
         plan_grid(config_of(flags), &lp);
         const int32_t nEc = (lp.w + 1) / 2;
         const int sv = dwt2::subband_vec(dwt2::kConfigs[config_of(flags)]);
-        lp.vec = aligned(lp.in, sv * es) && lp.in_pitch % sv == 0 && nEc % sv == 0 &&
-                 aligned(lp.in_ll, sv * es) && lp.in_ll_pitch % sv == 0 &&
-                 aligned(lp.out, 4 * es) && lp.out_pitch % 4 == 0;
-        const int rc = report(dwt2::launch_level(dir, to_wav(wavelet), to_dtype(dtype),
-                                                 (flags & DWT2_FLAG_SPLIT) != 0, config_of(flags), lp, s));
+        lp.vec = aligned(lp.in, sv * es) && lp.in_pitch % sv == 0 && stride_ok(planes, lp.in_ps, sv) &&
+                 nEc % sv == 0 && aligned(lp.in_ll, sv * es) && lp.in_ll_pitch % sv == 0 &&
+                 stride_ok(planes, lp.in_ll_ps, sv) && aligned(lp.out, 4 * es) && lp.out_pitch % 4 == 0 &&
+                 stride_ok(planes, lp.out_ps, 4);
+        const int rc = launch_planes(dir, wavelet, dtype, flags, lp, planes, es, s);
         if (rc) return rc;
         ll = lp.out;
         ll_pitch = lp.out_pitch;
+        ll_ps = lp.out_ps;
     }
     return DWT2_OK;
 }
@@ -234,53 +287,80 @@ extern "C" {
 
 int dwt2_max_levels(int32_t height, int32_t width) { return max_levels(height, width); }
 
-int dwt2_workspace_bytes(int32_t height, int32_t width, int levels, dwt2_dtype dtype,
-                         size_t* bytes) {
+int dwt2_workspace_bytes_planes(int32_t height, int32_t width, int levels, dwt2_dtype dtype, int32_t planes,
+                                size_t* bytes) {
     if (!bytes) return DWT2_E_NULL;
     *bytes = 0;
     const size_t es = elem_size(dtype);
     if (!es) return DWT2_E_DTYPE;
+    if (planes < 1) return DWT2_E_COUNT;
     if (height < 2 || width < 2 || height > kMaxSide || width > kMaxSide) return DWT2_E_SHAPE;
     if (levels < 1 || levels > max_levels(height, width)) return DWT2_E_LEVELS;
     Plan p;
     plan_levels(height, width, levels, &p);
-    size_t off_b = 0, total = 0;
-    ws_layout(p, es, &off_b, &total);
-    *bytes = total;
+    *bytes = ws_layout(p, es, planes).total;
     return DWT2_OK;
+}
+
+int dwt2_workspace_bytes(int32_t height, int32_t width, int levels, dwt2_dtype dtype, size_t* bytes) {
+    return dwt2_workspace_bytes_planes(height, width, levels, dtype, 1, bytes);
+}
+
+int dwt2_fwd_planes(const void* src, void* dst, int32_t planes, int64_t src_plane_stride, int64_t dst_plane_stride,
+                    int32_t height, int32_t width, int64_t src_pitch, int64_t dst_pitch, dwt2_dtype dtype,
+                    dwt2_wavelet wavelet, int levels, dwt2_boundary boundary, unsigned flags, void* workspace,
+                    size_t workspace_bytes, void* stream) {
+    const int rc = validate(src, dst, planes, src_plane_stride, dst_plane_stride, height, width, src_pitch,
+                            dst_pitch, dtype, wavelet, levels, boundary, flags, workspace, workspace_bytes, false);
+    if (rc) return rc;
+    return run_forward(src, dst, planes, src_plane_stride, dst_plane_stride, height, width, src_pitch, dst_pitch,
+                       dtype, wavelet, levels, flags, workspace, (hipStream_t)stream);
+}
+
+int dwt2_inv_planes(const void* src, void* dst, int32_t planes, int64_t src_plane_stride, int64_t dst_plane_stride,
+                    int32_t height, int32_t width, int64_t src_pitch, int64_t dst_pitch, dwt2_dtype dtype,
+                    dwt2_wavelet wavelet, int levels, dwt2_boundary boundary, unsigned flags, void* workspace,
+                    size_t workspace_bytes, void* stream) {
+    const int rc = validate(src, dst, planes, src_plane_stride, dst_plane_stride, height, width, src_pitch,
+                            dst_pitch, dtype, wavelet, levels, boundary, flags, workspace, workspace_bytes, false);
+    if (rc) return rc;
+    return run_backward(dwt2::kInverse, src, dst, planes, src_plane_stride, dst_plane_stride, height, width,
+                        src_pitch, dst_pitch, dtype, wavelet, levels, flags, workspace, (hipStream_t)stream);
+}
+
+int dwt2_adj_planes(const void* src, void* dst, int32_t planes, int64_t src_plane_stride, int64_t dst_plane_stride,
+                    int32_t height, int32_t width, int64_t src_pitch, int64_t dst_pitch, dwt2_dtype dtype,
+                    dwt2_wavelet wavelet, int levels, dwt2_boundary boundary, unsigned flags, void* workspace,
+                    size_t workspace_bytes, void* stream) {
+    const int rc = validate(src, dst, planes, src_plane_stride, dst_plane_stride, height, width, src_pitch,
+                            dst_pitch, dtype, wavelet, levels, boundary, flags, workspace, workspace_bytes, true);
+    if (rc) return rc;
+    return run_backward(dwt2::kAdjoint, src, dst, planes, src_plane_stride, dst_plane_stride, height, width,
+                        src_pitch, dst_pitch, dtype, wavelet, levels, flags, workspace, (hipStream_t)stream);
 }
 
 int dwt2_fwd(const void* src, void* dst, int32_t height, int32_t width, int64_t src_pitch,
              int64_t dst_pitch, dwt2_dtype dtype, dwt2_wavelet wavelet, int levels,
              dwt2_boundary boundary, unsigned flags, void* workspace, size_t workspace_bytes,
              void* stream) {
-    const int rc = validate(src, dst, height, width, src_pitch, dst_pitch, dtype, wavelet, levels,
-                            boundary, flags, workspace, workspace_bytes, false);
-    if (rc) return rc;
-    return run_forward(src, dst, height, width, src_pitch, dst_pitch, dtype, wavelet, levels,
-                       flags, workspace, (hipStream_t)stream);
+    return dwt2_fwd_planes(src, dst, 1, 0, 0, height, width, src_pitch, dst_pitch, dtype, wavelet, levels, boundary,
+                           flags, workspace, workspace_bytes, stream);
 }
 
 int dwt2_inv(const void* src, void* dst, int32_t height, int32_t width, int64_t src_pitch,
              int64_t dst_pitch, dwt2_dtype dtype, dwt2_wavelet wavelet, int levels,
              dwt2_boundary boundary, unsigned flags, void* workspace, size_t workspace_bytes,
              void* stream) {
-    const int rc = validate(src, dst, height, width, src_pitch, dst_pitch, dtype, wavelet, levels,
-                            boundary, flags, workspace, workspace_bytes, false);
-    if (rc) return rc;
-    return run_backward(dwt2::kInverse, src, dst, height, width, src_pitch, dst_pitch, dtype,
-                        wavelet, levels, flags, workspace, (hipStream_t)stream);
+    return dwt2_inv_planes(src, dst, 1, 0, 0, height, width, src_pitch, dst_pitch, dtype, wavelet, levels, boundary,
+                           flags, workspace, workspace_bytes, stream);
 }
 
 int dwt2_adj(const void* src, void* dst, int32_t height, int32_t width, int64_t src_pitch,
              int64_t dst_pitch, dwt2_dtype dtype, dwt2_wavelet wavelet, int levels,
              dwt2_boundary boundary, unsigned flags, void* workspace, size_t workspace_bytes,
              void* stream) {
-    const int rc = validate(src, dst, height, width, src_pitch, dst_pitch, dtype, wavelet, levels,
-                            boundary, flags, workspace, workspace_bytes, true);
-    if (rc) return rc;
-    return run_backward(dwt2::kAdjoint, src, dst, height, width, src_pitch, dst_pitch, dtype,
-                        wavelet, levels, flags, workspace, (hipStream_t)stream);
+    return dwt2_adj_planes(src, dst, 1, 0, 0, height, width, src_pitch, dst_pitch, dtype, wavelet, levels, boundary,
+                           flags, workspace, workspace_bytes, stream);
 }
 
 int dwt2_kernel_config(int index, int* algorithm, int* waves, int* rows, int* core_cols, int* core_rows) {

@@ -3,17 +3,18 @@
 
 namespace dwt2 {
 
-hipError_t launch_fwd(Wavelet wav, Dtype dt, bool split, int cfg, const LevelParams& p, hipStream_t s);
-hipError_t launch_inv(Wavelet wav, Dtype dt, bool split, int cfg, const LevelParams& p, hipStream_t s);
-hipError_t launch_adj(Wavelet wav, Dtype dt, bool split, int cfg, const LevelParams& p, hipStream_t s);
+hipError_t launch_fwd(Wavelet wav, Dtype dt, bool split, int cfg, const LevelParams& p, int planes, hipStream_t s);
+hipError_t launch_inv(Wavelet wav, Dtype dt, bool split, int cfg, const LevelParams& p, int planes, hipStream_t s);
+hipError_t launch_adj(Wavelet wav, Dtype dt, bool split, int cfg, const LevelParams& p, int planes, hipStream_t s);
 
 hipError_t launch_level(Direction dir, Wavelet wav, Dtype dt, bool split, int cfg,
-                        const LevelParams& p, hipStream_t stream) {
-    if (p.tiles_x <= 0 || p.tiles_y <= 0) return hipSuccess;
+                        const LevelParams& p, int planes, hipStream_t stream) {
+    if (p.tiles_x <= 0 || p.tiles_y <= 0 || planes <= 0) return hipSuccess;
+    if (planes > kMaxGridPlanes) return hipErrorInvalidValue;
     switch (dir) {
-        case kForward: return launch_fwd(wav, dt, split, cfg, p, stream);
-        case kInverse: return launch_inv(wav, dt, split, cfg, p, stream);
-        case kAdjoint: return launch_adj(wav, dt, split, cfg, p, stream);
+        case kForward: return launch_fwd(wav, dt, split, cfg, p, planes, stream);
+        case kInverse: return launch_inv(wav, dt, split, cfg, p, planes, stream);
+        case kAdjoint: return launch_adj(wav, dt, split, cfg, p, planes, stream);
     }
     return hipErrorInvalidValue;
 }

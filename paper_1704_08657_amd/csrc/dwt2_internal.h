@@ -72,14 +72,19 @@ struct LevelParams {
     int32_t tiles_x, tiles_y;
     int32_t vec;       // 1: every row base is aligned for vector access
     int32_t seg_rows;  // kAlgoStream: block rows per segment
+    // Plane batch: the launch covers gridDim.y planes; plane p's buffers
+    // start p * (stride) elements after those of plane 0.
+    int64_t in_ps, in_ll_ps, out_ps, out_ll_ps;
 };
 
-// Enqueue one level.  Returns hipSuccess or the launch error.
-// `cfg` indexes kConfigs; tiles_x / tiles_y (and seg_rows) of `p` must
-// follow it: for kAlgoTile the tile grid, for kAlgoStream the number of
-// strip groups (ceil(strips / waves)) and of segments.
+// Enqueue one level for `planes` planes (1 <= planes <= kMaxGridPlanes).
+// Returns hipSuccess or the launch error.  `cfg` indexes kConfigs;
+// tiles_x / tiles_y (and seg_rows) of `p` must follow it: for kAlgoTile the
+// tile grid, for kAlgoStream the number of strip groups (ceil(strips /
+// waves)) and of segments.
+constexpr int kMaxGridPlanes = 65535;
 hipError_t launch_level(Direction dir, Wavelet wav, Dtype dt, bool split, int cfg,
-                        const LevelParams& p, hipStream_t stream);
+                        const LevelParams& p, int planes, hipStream_t stream);
 
 // Batched forward CDF 9/7 (planner + one launch per level) for the tile
 // kernel configurations (batched_config_supported).

@@ -1121,6 +1121,20 @@ __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
     }
 }
 
+// The level parameters of plane `pl` of a plane batch (buffers offset by
+// the plane strides).
+template <typename T>
+__device__ __forceinline__ LevelParams plane_params(const LevelParams& P, int pl) {
+    LevelParams Q = P;
+    if (pl > 0) {
+        if (P.in) Q.in = static_cast<const T*>(P.in) + (int64_t)pl * P.in_ps;
+        if (P.in_ll) Q.in_ll = static_cast<const T*>(P.in_ll) + (int64_t)pl * P.in_ll_ps;
+        if (P.out) Q.out = static_cast<T*>(P.out) + (int64_t)pl * P.out_ps;
+        if (P.out_ll) Q.out_ll = static_cast<T*>(P.out_ll) + (int64_t)pl * P.out_ll_ps;
+    }
+    return Q;
+}
+
 template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K, int BPL>
 __global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
     using V = typename St<T>::V;
@@ -1140,7 +1154,7 @@ __global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
     if (t >= nt) return;                          // uniform over the work-group
     const int ty = t / P.tiles_x;
     const int tx = t - ty * P.tiles_x;
-    tile_body<DIR, WAV, T, SPLIT, NW, K, BPL>(P, tx, ty, lds, lane, wv);
+    tile_body<DIR, WAV, T, SPLIT, NW, K, BPL>(plane_params<T>(P, (int)blockIdx.y), tx, ty, lds, lane, wv);
 }
 
 // ===========================================================================
@@ -1409,7 +1423,8 @@ __device__ __forceinline__ void stream_segment(const LevelParams& P, const Geo& 
 }
 
 template <int DIR, int WAV, typename T, bool SPLIT, int W, int PF>
-__global__ void __launch_bounds__(W * kLanes) stream_kernel(LevelParams P) {
+__global__ void __launch_bounds__(W * kLanes) stream_kernel(LevelParams P0) {
+    const LevelParams P = plane_params<T>(P0, (int)blockIdx.y);
     const int lane = threadIdx.x & (kLanes - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
     // consecutive work-groups of one XCD take vertically adjacent segments,

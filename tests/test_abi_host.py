@@ -154,3 +154,29 @@ def test_kernel_configs_listed():
         st, algo, waves, rows, cc, cr = d.dwt2_kernel_config(i)
         assert st == 0 and algo in (d.DWT2_ALGO_TILE, d.DWT2_ALGO_STREAM) and waves >= 1 and cr >= 1
     assert d.dwt2_kernel_config(d.DWT2_NUM_KERNEL_CONFIGS)[0] == -11
+
+
+def test_plane_batch_argument_errors():
+    L = d.lib()
+    n = ctypes.c_size_t(0)
+    assert L.dwt2_workspace_bytes_planes(64, 64, 2, d.DWT2_F32, 3, ctypes.byref(n)) == 0
+    one = ctypes.c_size_t(0)
+    assert L.dwt2_workspace_bytes_planes(64, 64, 2, d.DWT2_F32, 1, ctypes.byref(one)) == 0
+    assert n.value == 3 * one.value > 0               # one pair of LL buffers per plane
+    assert L.dwt2_workspace_bytes_planes(64, 64, 2, d.DWT2_F32, 0, ctypes.byref(n)) == -12
+    need = L.dwt2_workspace_bytes_planes(64, 64, 2, d.DWT2_F32, 3, ctypes.byref(n)) or n.value
+
+    def fp(fn=L.dwt2_fwd_planes, src=FAKE_SRC, dst=FAKE_DST, planes=3, sps=64 * 64, dps=64 * 64, levels=2,
+           ws=FAKE_WS, ws_n=need):
+        return fn(ctypes.c_void_p(src), ctypes.c_void_p(dst), planes, sps, dps, 64, 64, 64, 64, d.DWT2_F32,
+                  d.DWT2_CDF97, levels, 0, 0, ctypes.c_void_p(ws), ws_n, None)
+    for fn in (L.dwt2_fwd_planes, L.dwt2_inv_planes, L.dwt2_adj_planes):
+        assert fp(fn, planes=0) == -12
+        assert fp(fn, sps=64 * 64 - 1) == -7          # planes of src would overlap
+        assert fp(fn, dps=100) == -7
+        assert fp(fn, ws_n=need - 1) == -8
+        assert fp(fn, dst=FAKE_SRC + 2 * 64 * 64 * 4) == -9   # dst inside src's third plane
+        assert fp(fn, ws=FAKE_DST + 3 * 64 * 64 * 4 - 8) == -9
+    # one plane: the stride is not used
+    st, n1 = d.dwt2_workspace_bytes(64, 64, 2, d.DWT2_F32)
+    assert fp(planes=1, sps=0, dps=0, ws_n=n1 - 1) == -8

@@ -295,3 +295,44 @@ def test_storage_bound_interior_tiles(tdt):
         say("storage interior", tdt, cfg)
         y = d.fwd(xs.to(dev()), "cdf97", lv, config=cfg)
         assert rel_err(host(y), ref) <= 8 * UNIT[tdt], cfg
+
+
+@pytest.mark.parametrize("tdt,min_psnr", [(torch.bfloat16, 48.0), (torch.float16, 64.0)])
+def test_precision_report_1024_5_levels(tdt, min_psnr):
+    """16-bit storage, 1024^2, 5 levels forward + inverse: coefficient max-abs
+    against the FP64 oracle of the storage-rounded input, and reconstruction
+    PSNR (peak 1.0) against that input.  The floors sit ~4 dB below the
+    values the arithmetic gives (about 52 dB BF16, 70 dB FP16)."""
+    n, lv = 1024, 5
+    xq = torch.from_numpy(workloads.uniform(n, n, seed=3)).to(tdt)
+    x64 = xq.to(torch.float64).numpy()
+    c = d.fwd(xq.to(dev()), "cdf97", lv)
+    ref = lifting.fwd(x64, "cdf97", lv)
+    err = float(np.abs(host(c) - ref).max())
+    r = host(d.inv(c, "cdf97", lv))
+    psnr = 10 * np.log10(1.0 / float(((r - x64) ** 2).mean()))
+    say("precision", tdt, "coeff max-abs", err, "max |coeff|", float(np.abs(ref).max()), "PSNR dB", psnr)
+    assert err <= 8 * UNIT[tdt] * float(np.abs(ref).max())
+    assert psnr >= min_psnr
+
+
+@pytest.mark.parametrize("shape,lv", [((3, 37, 53), 3), ((5, 260, 2056), 2), ((2, 2, 3000), 1)])
+def test_plane_batch_equals_single_planes(shape, lv):
+    """A plane batch (one launch per level for all planes) equals the
+    single-image transform of every plane, bit for bit, in every direction
+    and kernel configuration; plane 0 is also checked against the oracle."""
+    n, h, w = shape
+    x = gpu(workloads.planes(n, h, w, seed=31))
+    xi = gpu(np.stack([workloads.pixels_u8(h, w, seed=32 + k) for k in range(n)]))
+    for cfg in range(d.DWT2_NUM_KERNEL_CONFIGS):
+        say("plane batch", shape, lv, cfg)
+        y = d.fwd(x, "cdf97", lv, config=cfg)
+        r = d.inv(y, "cdf97", lv, config=cfg)
+        a = d.adj(y, lv, config=cfg)
+        yi = d.fwd(xi, "cdf53", lv, config=cfg)
+        for k in range(n):
+            assert torch.equal(y[k], d.fwd(x[k], "cdf97", lv, config=cfg)), (cfg, k)
+            assert torch.equal(r[k], d.inv(y[k], "cdf97", lv, config=cfg)), (cfg, k)
+            assert torch.equal(a[k], d.adj(y[k], lv, config=cfg)), (cfg, k)
+            assert torch.equal(yi[k], d.fwd(xi[k], "cdf53", lv, config=cfg)), (cfg, k)
+    assert rel_err(host(y[0]), lifting.fwd(host(x[0]), "cdf97", lv)) <= TOL97
