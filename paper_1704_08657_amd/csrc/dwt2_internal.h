@@ -72,9 +72,12 @@ struct LevelParams {
     int32_t tiles_x, tiles_y;
     int32_t vec;       // 1: every row base is aligned for vector access
     int32_t seg_rows;  // kAlgoStream: block rows per segment
-    // Plane batch: the launch covers gridDim.y planes; plane p's buffers
-    // start p * (stride) elements after those of plane 0.
+    // Plane batch: the launch covers `planes` planes; plane p's buffers
+    // start p * (stride) elements after those of plane 0.  Set by the
+    // launcher (the tile kernel deals the tiles of all planes as one list,
+    // the streaming kernel takes one grid row per plane).
     int64_t in_ps, in_ll_ps, out_ps, out_ll_ps;
+    int32_t planes;
 };
 
 // Enqueue one level for `planes` planes (1 <= planes <= kMaxGridPlanes).

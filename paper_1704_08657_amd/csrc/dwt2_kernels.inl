@@ -1147,14 +1147,18 @@ __global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
     // re-reads stay in that XCD's L2 (and vertical ones within a chunk),
     // while the 8 XCDs work on adjacent chunks, so the image is swept by
     // one narrow window (8 chunks tall) rather than 8 distant ones.
+    // The tiles of a plane batch form one list, plane after plane, dealt
+    // the same way: small planes do not each round up to 8 chunks.
     const int nt = P.tiles_x * P.tiles_y;
     const int chunk = kRemapRows * P.tiles_x;
     const int j = (int)(blockIdx.x >> 3);
-    const int t = ((j / chunk) * 8 + (int)(blockIdx.x & 7)) * chunk + j % chunk;
-    if (t >= nt) return;                          // uniform over the work-group
+    const int g = ((j / chunk) * 8 + (int)(blockIdx.x & 7)) * chunk + j % chunk;
+    if (g >= nt * P.planes) return;               // uniform over the work-group
+    const int pl = g / nt;
+    const int t = g - pl * nt;
     const int ty = t / P.tiles_x;
     const int tx = t - ty * P.tiles_x;
-    tile_body<DIR, WAV, T, SPLIT, NW, K, BPL>(plane_params<T>(P, (int)blockIdx.y), tx, ty, lds, lane, wv);
+    tile_body<DIR, WAV, T, SPLIT, NW, K, BPL>(plane_params<T>(P, pl), tx, ty, lds, lane, wv);
 }
 
 // ===========================================================================

@@ -7,21 +7,39 @@ namespace kern {
 
 template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K, int BPL>
 hipError_t launch_shape(const LevelParams& p, int planes, hipStream_t s) {
-    // a multiple of 8 chunks of kRemapRows tile rows (see level_kernel)
+    // the tiles of all planes, rounded up to a multiple of 8 chunks of
+    // kRemapRows tile rows (see level_kernel); planes beyond what one grid
+    // holds go to further launches
+    const int64_t nt = (int64_t)p.tiles_x * p.tiles_y;
     const int64_t chunk = (int64_t)kRemapRows * p.tiles_x;
-    const int64_t chunks = (p.tiles_y + kRemapRows - 1) / kRemapRows;
-    const int64_t grid = (chunks + 7) / 8 * 8 * chunk;
-    if (grid > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((level_kernel<DIR, WAV, T, SPLIT, NW, K, BPL>), dim3((unsigned)grid, (unsigned)planes),
-                       dim3(NW * kLanes), 0, s, p);
-    return hipGetLastError();
+    const int64_t limit = 0x7fffffff - 8 * chunk;
+    if (nt < 1 || nt > limit) return hipErrorInvalidConfiguration;
+    const int64_t per = limit / nt;
+    for (int64_t p0 = 0; p0 < planes; p0 += per) {
+        LevelParams q = p;
+        q.planes = (int32_t)(planes - p0 < per ? planes - p0 : per);
+        if (p0 > 0) {
+            if (q.in) q.in = static_cast<const T*>(q.in) + p0 * q.in_ps;
+            if (q.in_ll) q.in_ll = static_cast<const T*>(q.in_ll) + p0 * q.in_ll_ps;
+            if (q.out) q.out = static_cast<T*>(q.out) + p0 * q.out_ps;
+            if (q.out_ll) q.out_ll = static_cast<T*>(q.out_ll) + p0 * q.out_ll_ps;
+        }
+        const int64_t grid = (nt * q.planes + 8 * chunk - 1) / (8 * chunk) * (8 * chunk);
+        hipLaunchKernelGGL((level_kernel<DIR, WAV, T, SPLIT, NW, K, BPL>), dim3((unsigned)grid),
+                           dim3(NW * kLanes), 0, s, q);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int DIR, int WAV, typename T, bool SPLIT, int W, int PF>
 hipError_t launch_stream(const LevelParams& p, int planes, hipStream_t s) {
     const int nt = p.tiles_x * p.tiles_y;
     const int grid = ((nt + 7) >> 3) * 8;
-    hipLaunchKernelGGL((stream_kernel<DIR, WAV, T, SPLIT, W, PF>), dim3(grid, planes), dim3(W * kLanes), 0, s, p);
+    LevelParams q = p;
+    q.planes = planes;
+    hipLaunchKernelGGL((stream_kernel<DIR, WAV, T, SPLIT, W, PF>), dim3(grid, planes), dim3(W * kLanes), 0, s, q);
     return hipGetLastError();
 }
 

@@ -62,25 +62,28 @@ int run(const std::vector<int>& H, const std::vector<int>& W, int levels, int cx
     }
     return bad;
 }
-// The single-image level kernel's grid and tile remap (chunks of
-// kRemapRows tile rows dealt over 8 XCDs) cover every tile exactly once.
+// The level kernel's grid and tile remap (chunks of kRemapRows tile rows
+// dealt over 8 XCDs, the tiles of a plane batch taken as one list) cover
+// every tile of every plane exactly once.
 int check_level_mapping() {
     int bad = 0;
-    for (int tiles_x = 1; tiles_x <= 40; tiles_x += 3)
-        for (int tiles_y = 1; tiles_y <= 700; tiles_y += 7) {
-            const int64_t chunk = (int64_t)kRemapRows * tiles_x;
-            const int64_t chunks = (tiles_y + kRemapRows - 1) / kRemapRows;
-            const int64_t grid = (chunks + 7) / 8 * 8 * chunk;
-            const int nt = tiles_x * tiles_y;
-            std::vector<int> seen(nt, 0);
-            for (int64_t b = 0; b < grid; ++b) {
-                const int j = (int)(b >> 3);
-                const int t = (int)(((j / chunk) * 8 + (b & 7)) * chunk + j % chunk);
-                if (t < 0) { bad++; continue; }
-                if (t < nt) seen[t]++;
+    for (int planes : {1, 2, 3, 5, 17})
+        for (int tiles_x = 1; tiles_x <= 40; tiles_x += 3)
+            for (int tiles_y = 1; tiles_y <= 700; tiles_y += 7) {
+                const int64_t chunk = (int64_t)kRemapRows * tiles_x;
+                const int nt = tiles_x * tiles_y;
+                const int64_t grid = ((int64_t)nt * planes + 8 * chunk - 1) / (8 * chunk) * (8 * chunk);
+                std::vector<int> seen((size_t)nt * planes, 0);
+                for (int64_t b = 0; b < grid; ++b) {
+                    const int j = (int)(b >> 3);
+                    const int g = (int)(((j / chunk) * 8 + (b & 7)) * chunk + j % chunk);
+                    if (g < 0) { bad++; continue; }
+                    if (g >= nt * planes) continue;
+                    const int pl = g / nt, t = g - pl * nt;
+                    seen[(size_t)pl * nt + t]++;
+                }
+                for (int v : seen) if (v != 1) { bad++; break; }
             }
-            for (int v : seen) if (v != 1) { bad++; break; }
-        }
     return bad;
 }
 int main() {
