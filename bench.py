@@ -12,7 +12,8 @@ level kernel (algorithmic bytes: each pixel read once, each coefficient
 written once = 2 * 4 B/px) and a `cpu_baseline` object (the CPU oracle timed
 on a bounded crop of the same image).  `forms` lists the other forms of the
 path, measured the same way with fewer steps: 5 levels, the P0/P1 split,
-inverse, BF16 / FP16 storage, reversible 5/3, warm and gradient-input
+inverse, the separable comparison scheme (twice the steps and barriers),
+BF16 / FP16 storage, reversible 5/3, warm and gradient-input
 variants, 1024^2 (per call and under graph replay), 4096^2 (cold and warm)
 and 16384^2 images, 3 x 8192^2 planes forward + inverse at each storage type
 with coefficient error and reconstruction PSNR, the autograd training step
@@ -212,6 +213,21 @@ def main():
              tune_key=None)
         form("cdf97 inv f32 1 level", lambda i, c: d.inv(ys[i % pairs], "cdf97", 1, out=xs[i % pairs], config=c),
              1, 4, tune_key=("inv", "cdf97", "f32"))
+        # the separable comparison scheme (8 steps and barriers per level
+        # instead of 4), same tile configuration as the fused forms
+        form("cdf97 fwd f32 1 level separable (8 barriers)",
+             lambda i, c: d.fwd(xs[i % pairs], "cdf97", 1, out=ys[i % pairs], config=c, separable=True), 1, 4)
+        form("cdf97 inv f32 1 level separable (8 barriers)",
+             lambda i, c: d.inv(ys[i % pairs], "cdf97", 1, out=xs[i % pairs], config=c, separable=True), 1, 4)
+        form("cdf97 fwd f32 5 levels separable (8 barriers)",
+             lambda i, c: d.fwd(xs[i % pairs], "cdf97", 5, out=ys[i % pairs], config=c, separable=True), 5, 4)
+        # the fused steps evaluated as their two 1-D factors (4 barriers)
+        form("cdf97 fwd f32 1 level factored (4 barriers)",
+             lambda i, c: d.fwd(xs[i % pairs], "cdf97", 1, out=ys[i % pairs], config=c, factored=True), 1, 4)
+        form("cdf97 inv f32 1 level factored (4 barriers)",
+             lambda i, c: d.inv(ys[i % pairs], "cdf97", 1, out=xs[i % pairs], config=c, factored=True), 1, 4)
+        form("cdf97 fwd f32 5 levels factored (4 barriers)",
+             lambda i, c: d.fwd(xs[i % pairs], "cdf97", 5, out=ys[i % pairs], config=c, factored=True), 5, 4)
         del ws5
         for tdt, nm in [(torch.bfloat16, "bf16"), (torch.float16, "f16")]:
             xb = [t.to(tdt) for t in xs]
@@ -228,6 +244,8 @@ def main():
              1, 4, tune_key=("fwd", "cdf53", "i32"))
         form("cdf53 inv i32 1 level", lambda i, c: d.inv(yi[i % pairs], "cdf53", 1, out=xi[i % pairs], config=c),
              1, 4, tune_key=("inv", "cdf53", "i32"))
+        form("cdf53 fwd i32 1 level separable (4 barriers)",
+             lambda i, c: d.fwd(xi[i % pairs], "cdf53", 1, out=yi[i % pairs], config=c, separable=True), 1, 4)
         del xi, yi
         form("cdf97 fwd f32 1 level, warm (one buffer pair, repeated)",
              lambda i, c: d.fwd(xs[0], "cdf97", 1, out=ys[0], config=c), 1, 4)

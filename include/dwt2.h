@@ -91,6 +91,27 @@ typedef enum {
                                 (Section "Optimization Approach"); CDF 9/7 only.
                                 Same values up to FP32 rounding; applied in tiles
                                 away from the image border.                    */
+#define DWT2_FLAG_SEPARABLE 2u  /* the comparison scheme of Section "Proposed
+                                Schemes": every fused step replaced by its
+                                horizontal and its vertical separable lifting
+                                step, one work-group barrier each (8 barriers
+                                per level for CDF 9/7, 4 for 5/3, against 4 and
+                                2).  Same values up to FP32 rounding (5/3:
+                                bit-identical).  dwt2_fwd / dwt2_inv (and their
+                                _planes forms) with a DWT2_ALGO_TILE
+                                configuration only; not with DWT2_FLAG_SPLIT. */
+#define DWT2_FLAG_FACTORED 4u   /* the fused steps of Section "Proposed
+                                Schemes" (one barrier each, as without the
+                                flag), each evaluated as its horizontal then
+                                its vertical factor in registers: a wave holds
+                                whole tile rows, so the horizontal factor needs
+                                no barrier, and the vertical factor reads the
+                                neighbour's intermediate instead of recomputing
+                                it.  8 operations per 2x2 block and fused step
+                                instead of 11 (the split: 9).  Same values up
+                                to FP32 rounding (5/3: bit-identical).  Same
+                                restrictions as DWT2_FLAG_SEPARABLE; not
+                                together with it.                            */
 /* Kernel configuration: bits 8..15 hold 1 + the index of a configuration
  * listed by dwt2_kernel_config(); 0 selects the library default.  Every
  * configuration computes the same values (bit-identical for the same other

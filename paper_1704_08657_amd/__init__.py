@@ -27,6 +27,8 @@ DWT2_CDF97, DWT2_CDF53_REV = 0, 1
 DWT2_F32, DWT2_BF16, DWT2_F16, DWT2_I32 = 0, 1, 2, 3
 DWT2_SYMMETRIC_WHOLE = 0
 DWT2_FLAG_SPLIT = 1
+DWT2_FLAG_SEPARABLE = 2
+DWT2_FLAG_FACTORED = 4
 DWT2_FLAG_KERNEL_SHIFT = 8
 DWT2_NUM_KERNEL_CONFIGS = 8
 DWT2_ALGO_TILE, DWT2_ALGO_STREAM = 0, 1
@@ -178,7 +180,7 @@ def tuned_config(direction: str, wavelet: str, dtype: int, h: int, w: int, level
     return autotune.lookup(direction, wavelet, _DTYPE_NAMES[dtype], h, w, levels)
 
 
-def _transform(fn, name, x, wavelet, levels, split, out, config=None):
+def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=False, factored=False):
     torch = _torch()
     _check(x)
     x2 = x.reshape(-1, *x.shape[-2:]) if x.is_contiguous() else x.contiguous().reshape(-1, *x.shape[-2:])
@@ -195,9 +197,12 @@ def _transform(fn, name, x, wavelet, levels, split, out, config=None):
     planes = x2.shape[0]
     dt = dtype_code(x2)
     stream = _stream_ptr(x2)
-    flags = DWT2_FLAG_SPLIT if split else 0
+    flags = ((DWT2_FLAG_SPLIT if split else 0) | (DWT2_FLAG_SEPARABLE if separable else 0)
+             | (DWT2_FLAG_FACTORED if factored else 0))
     if config is None:
         config = tuned_config(_DIRECTIONS[name], wavelet, dt, H, W, levels)
+        if (separable or factored) and config is not None and dwt2_kernel_config(config)[1] != DWT2_ALGO_TILE:
+            config = None                 # these schemes run on tile configurations
     if config is not None:
         flags |= DWT2_FLAG_KERNEL(config)
     # one call for all planes (at most 2^31 - 1 per call)
@@ -215,16 +220,24 @@ def _transform(fn, name, x, wavelet, levels, split, out, config=None):
     return out.reshape(x.shape)
 
 
-def fwd(x, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None):
+def fwd(x, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None,
+        separable: bool = False, factored: bool = False):
     """Forward transform of every [H, W] plane of x into a Mallat pyramid
     (all planes in one call: one launch per level).  `config` selects a
-    kernel configuration index (None: tuned or library default)."""
-    return _transform(lib().dwt2_fwd_planes, "dwt2_fwd", x, wavelet, levels, split, out, config)
+    kernel configuration index (None: tuned or library default).  At most
+    one of `split` (the P0/P1 operation-count reduction), `separable` (the
+    separable comparison scheme, twice the barriers) and `factored` (each
+    fused step evaluated as its two 1-D factors, one barrier per step); all
+    compute the same values up to FP32 rounding."""
+    return _transform(lib().dwt2_fwd_planes, "dwt2_fwd", x, wavelet, levels, split, out, config, separable,
+                      factored)
 
 
-def inv(c, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None):
+def inv(c, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None,
+        separable: bool = False, factored: bool = False):
     """Inverse transform of every [H, W] Mallat pyramid of c."""
-    return _transform(lib().dwt2_inv_planes, "dwt2_inv", c, wavelet, levels, split, out, config)
+    return _transform(lib().dwt2_inv_planes, "dwt2_inv", c, wavelet, levels, split, out, config, separable,
+                      factored)
 
 
 def adj(g, levels: int = 1, out=None, config=None):

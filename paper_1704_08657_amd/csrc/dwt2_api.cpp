@@ -101,6 +101,19 @@ size_t planes_span_bytes(int32_t planes, int64_t plane_stride, int32_t h, int32_
     return (size_t)(planes - 1) * (size_t)plane_stride * es + span_bytes(h, w, pitch, es);
 }
 
+// Kernel configuration selected by the flags (0 in the field = default).
+int config_of(unsigned flags) {
+    const unsigned t = (flags & DWT2_FLAG_KERNEL_MASK) >> DWT2_FLAG_KERNEL_SHIFT;
+    return t == 0 ? dwt2::kDefaultConfig : (int)t - 1;
+}
+
+dwt2::Scheme scheme_of(unsigned flags) {
+    if (flags & DWT2_FLAG_SPLIT) return dwt2::kSchemeSplit;
+    if (flags & DWT2_FLAG_SEPARABLE) return dwt2::kSchemeSeparable;
+    if (flags & DWT2_FLAG_FACTORED) return dwt2::kSchemeFactored;
+    return dwt2::kSchemeFused;
+}
+
 int validate(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dps, int32_t h, int32_t w,
              int64_t sp, int64_t dp, int dtype, int wavelet, int levels, int boundary, unsigned flags,
              const void* ws, size_t ws_bytes, bool adjoint) {
@@ -111,10 +124,18 @@ int validate(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dp
         return DWT2_E_DTYPE;
     if ((wavelet == DWT2_CDF53_REV) != (dtype == DWT2_I32)) return DWT2_E_DTYPE;
     if (boundary != DWT2_SYMMETRIC_WHOLE) return DWT2_E_BOUNDARY;
-    if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_KERNEL_MASK)) return DWT2_E_FLAGS;
+    if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED | DWT2_FLAG_KERNEL_MASK))
+        return DWT2_E_FLAGS;
     if (((flags & DWT2_FLAG_KERNEL_MASK) >> DWT2_FLAG_KERNEL_SHIFT) > (unsigned)dwt2::kNumConfigs)
         return DWT2_E_FLAGS;
     if ((flags & DWT2_FLAG_SPLIT) && (wavelet != DWT2_CDF97 || adjoint)) return DWT2_E_FLAGS;
+    // at most one scheme flag; the separable and factored schemes: forward /
+    // inverse on tile configurations
+    const unsigned schemes = flags & (DWT2_FLAG_SPLIT | DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED);
+    if (schemes & (schemes - 1)) return DWT2_E_FLAGS;
+    if ((flags & (DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED)) &&
+        (adjoint || dwt2::kConfigs[config_of(flags)].algo != dwt2::kAlgoTile))
+        return DWT2_E_FLAGS;
     if (adjoint && wavelet != DWT2_CDF97) return DWT2_E_WAVELET;
     if (h < 2 || w < 2 || h > kMaxSide || w > kMaxSide) return DWT2_E_SHAPE;
     if (sp < w || dp < w) return DWT2_E_PITCH;
@@ -162,12 +183,6 @@ void plan_grid(int cfg, dwt2::LevelParams* lp) {
     }
 }
 
-// Kernel configuration selected by the flags (0 in the field = default).
-int config_of(unsigned flags) {
-    const unsigned t = (flags & DWT2_FLAG_KERNEL_MASK) >> DWT2_FLAG_KERNEL_SHIFT;
-    return t == 0 ? dwt2::kDefaultConfig : (int)t - 1;
-}
-
 // Launch one level for every plane, in grid chunks of at most
 // kMaxGridPlanes planes.
 int launch_planes(dwt2::Direction dir, int wavelet, int dtype, unsigned flags, dwt2::LevelParams lp,
@@ -181,8 +196,8 @@ int launch_planes(dwt2::Direction dir, int wavelet, int dtype, unsigned flags, d
             q.out = lp.out ? (char*)lp.out + (size_t)p0 * (size_t)lp.out_ps * es : nullptr;
             q.out_ll = lp.out_ll ? (char*)lp.out_ll + (size_t)p0 * (size_t)lp.out_ll_ps * es : nullptr;
         }
-        const int rc = report(dwt2::launch_level(dir, to_wav(wavelet), to_dtype(dtype),
-                                                 (flags & DWT2_FLAG_SPLIT) != 0, config_of(flags), q, n, s));
+        const int rc = report(dwt2::launch_level(dir, to_wav(wavelet), to_dtype(dtype), scheme_of(flags),
+                                                 config_of(flags), q, n, s));
         if (rc) return rc;
     }
     return DWT2_OK;

@@ -136,7 +136,7 @@ batched_level_kernel(const dwt2_image* imgs, int count, int levels, int l, unsig
             P.out_ll_pitch % BPL == 0;
     const int ty = tt / P.tiles_x;
     const int tx = tt - ty * P.tiles_x;
-    tile_body<kForward, kCdf97, T, SPLIT, NW, K, BPL>(P, tx, ty, lds, lane, wv);
+    tile_body<kForward, kCdf97, T, SPLIT ? kSchemeSplit : kSchemeFused, NW, K, BPL>(P, tx, ty, lds, lane, wv);
 }
 
 template <typename T, bool SPLIT, int NW, int K, int BPL>

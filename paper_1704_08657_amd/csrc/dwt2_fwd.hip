@@ -3,8 +3,8 @@
 
 namespace dwt2 {
 
-hipError_t launch_fwd(Wavelet wav, Dtype dt, bool split, int cfg, const LevelParams& p, int planes, hipStream_t s) {
-    return kern::launch_dir<kForward>(wav, dt, split, cfg, p, planes, s);
+hipError_t launch_fwd(Wavelet wav, Dtype dt, Scheme sch, int cfg, const LevelParams& p, int planes, hipStream_t s) {
+    return kern::launch_dir<kForward>(wav, dt, sch, cfg, p, planes, s);
 }
 
 }  // namespace dwt2

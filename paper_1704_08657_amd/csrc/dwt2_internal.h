@@ -12,6 +12,12 @@ namespace dwt2 {
 enum Direction : int { kForward = 0, kInverse = 1, kAdjoint = 2 };
 enum Wavelet : int { kCdf97 = 0, kCdf53 = 1 };
 enum Dtype : int { kF32 = 0, kBF16 = 1, kF16 = 2, kI32 = 3 };
+// Lifting scheme of a level: the fused non-separable steps, the fused steps
+// with the P0/P1 split, the separable steps (the comparison scheme: every
+// fused step replaced by its horizontal and its vertical step, a barrier
+// each), or the fused steps evaluated as those two factors in registers (one
+// barrier per fused step: the horizontal factor never leaves the wave).
+enum Scheme : int { kSchemeFused = 0, kSchemeSplit = 1, kSchemeSeparable = 2, kSchemeFactored = 3 };
 
 // Geometry shared by host planning and the kernels, in blocks of 2x2 pixels.
 // A tile (kAlgoTile) has 64 * bpl output columns (bpl blocks per lane) and
@@ -86,7 +92,8 @@ struct LevelParams {
 // tile grid, for kAlgoStream the number of strip groups (ceil(strips /
 // waves)) and of segments.
 constexpr int kMaxGridPlanes = 65535;
-hipError_t launch_level(Direction dir, Wavelet wav, Dtype dt, bool split, int cfg,
+// kSchemeSeparable and kSchemeFactored run on the tile configurations only.
+hipError_t launch_level(Direction dir, Wavelet wav, Dtype dt, Scheme scheme, int cfg,
                         const LevelParams& p, int planes, hipStream_t stream);
 
 // Batched forward CDF 9/7 (planner + one launch per level) for the tile

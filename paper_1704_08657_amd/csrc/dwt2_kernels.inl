@@ -136,7 +136,14 @@ enum Kind : int {
     kSplit = 2,      // nonlocal P1 / U1 part of the split
     kAdj = 3,        // transposed step with transposed border weights
     kIntFwd = 4,     // reversible 5/3 forward (with neighbour recomputation)
-    kIntInv = 5      // reversible 5/3 inverse
+    kIntInv = 5,     // reversible 5/3 inverse
+    // separable steps (the comparison scheme): one axis per step
+    kSepH = 6,       // float horizontal step (coefficient sign as given)
+    kSepV = 7,       // float vertical step
+    kSepHInt = 8,    // reversible 5/3 forward, horizontal
+    kSepVInt = 9,    // reversible 5/3 forward, vertical
+    kSepHIntInv = 10,  // reversible 5/3 inverse, horizontal
+    kSepVIntInv = 11   // reversible 5/3 inverse, vertical
 };
 
 template <typename V> struct alignas(4 * sizeof(V)) Vec4 { V a, b, c, d; };
@@ -204,6 +211,24 @@ __device__ __forceinline__ void plus_block(V& x0, V& x1, V& x2, V& x3,
             x1 = x1 + ((x0 + x0R) >> 1);
             x3 = x3h + ((x2v + x2Rv) >> 1);
             x2 = x2v;
+        } else if constexpr (KIND == kSepH) {        // T^H: odd columns from the even ones
+            x1 = fmaf(c, x0 + x0R, x1);
+            x3 = fmaf(c, x2 + x2R, x3);
+        } else if constexpr (KIND == kSepV) {        // T^V: odd rows from the even ones
+            x2 = fmaf(c, x0 + x0D, x2);
+            x3 = fmaf(c, x1 + x1D, x3);
+        } else if constexpr (KIND == kSepHInt) {
+            x1 = x1 - ((x0 + x0R) >> 1);
+            x3 = x3 - ((x2 + x2R) >> 1);
+        } else if constexpr (KIND == kSepVInt) {
+            x2 = x2 - ((x0 + x0D) >> 1);
+            x3 = x3 - ((x1 + x1D) >> 1);
+        } else if constexpr (KIND == kSepHIntInv) {
+            x1 = x1 + ((x0 + x0R) >> 1);
+            x3 = x3 + ((x2 + x2R) >> 1);
+        } else if constexpr (KIND == kSepVIntInv) {
+            x2 = x2 + ((x0 + x0D) >> 1);
+            x3 = x3 + ((x1 + x1D) >> 1);
         }
     }
 }
@@ -282,6 +307,24 @@ __device__ __forceinline__ void minus_block(V& x0, V& x1, V& x2, V& x3,
             x0 = x0v - ((x1vl + x1vo + 2) >> 2);
             x2 = x2 - ((X3oo + X3ol + 2) >> 2);
             x1 = x1v_own;
+        } else if constexpr (KIND == kSepH) {        // S^H: even columns from the odd ones
+            x0 = fmaf(c, x1lc + x1o, x0);
+            x2 = fmaf(c, X3oo + X3ol, x2);
+        } else if constexpr (KIND == kSepV) {        // S^V: even rows from the odd ones
+            x0 = fmaf(c, x2uc + x2o, x0);
+            x1 = fmaf(c, X3oo + X3uo, x1);
+        } else if constexpr (KIND == kSepHInt) {
+            x0 = x0 + ((x1lc + x1o + 2) >> 2);
+            x2 = x2 + ((X3oo + X3ol + 2) >> 2);
+        } else if constexpr (KIND == kSepVInt) {
+            x0 = x0 + ((x2uc + x2o + 2) >> 2);
+            x1 = x1 + ((X3oo + X3uo + 2) >> 2);
+        } else if constexpr (KIND == kSepHIntInv) {
+            x0 = x0 - ((x1lc + x1o + 2) >> 2);
+            x2 = x2 - ((X3oo + X3ol + 2) >> 2);
+        } else if constexpr (KIND == kSepVIntInv) {
+            x0 = x0 - ((x2uc + x2o + 2) >> 2);
+            x1 = x1 - ((X3oo + X3uo + 2) >> 2);
         }
     }
 }
@@ -433,14 +476,18 @@ template <int BPL> struct TileGeo {
 };
 
 // Before the barrier of a predict-shaped step: the wave's top rows (core and
-// halo) for the wave above, and the exchange columns for this wave: core
-// column 0 (x0, x2 of every row, read by the left halo lanes) and halo
-// column 64*BPL (x0, x2, read by lane 63).
-template <int NW, int BPL, int K, typename V>
+// halo) for the wave above (PV), and the exchange columns for this wave (PH):
+// core column 0 (x0, x2 of every row, read by the left halo lanes) and halo
+// column 64*BPL (x0, x2, read by lane 63).  A fused step needs both; a
+// separable step only those of its own axis.
+template <int NW, int BPL, int K, bool PH = true, bool PV = true, typename V>
 __device__ __forceinline__ void publish_plus(const V (&a)[K][Lay<BPL>::BX], const V (&e)[8],
                                              TileLds<V, NW, BPL, K>& L, int lane, int wv) {
-    publish_row<BPL>(a[0], 0, L.t[wv], lane);
-    if (lane < 32 && (lane & 15) == 0) L.et[wv][lane >> 4] = Vec4<V>{e[0], e[1], e[4], e[5]};
+    if constexpr (PV) {
+        publish_row<BPL>(a[0], 0, L.t[wv], lane);
+        if (lane < 32 && (lane & 15) == 0) L.et[wv][lane >> 4] = Vec4<V>{e[0], e[1], e[4], e[5]};
+    }
+    if constexpr (!PH) return;
     if (lane == 0) {
 #pragma unroll
         for (int r = 0; r < K; r += 2) {
@@ -457,12 +504,15 @@ __device__ __forceinline__ void publish_plus(const V (&a)[K][Lay<BPL>::BX], cons
 // Before the barrier of an update-shaped step: the bottom rows for the wave
 // below, core column 64*BPL - 1 (x1, x3, read by the right halo lanes) and
 // halo column -1 (x1, x3, read by lane 0).
-template <int NW, int BPL, int K, typename V>
+template <int NW, int BPL, int K, bool PH = true, bool PV = true, typename V>
 __device__ __forceinline__ void publish_minus(const V (&a)[K][Lay<BPL>::BX], const V (&e)[8],
                                               TileLds<V, NW, BPL, K>& L, int lane, int wv) {
     using Ly = Lay<BPL>;
-    publish_row<BPL>(a[K - 1], 2, L.s[wv + 1], lane);
-    if (lane < 32 && (lane & 15) == K - 1) L.es[wv + 1][lane >> 4] = Vec4<V>{e[2], e[3], e[6], e[7]};
+    if constexpr (PV) {
+        publish_row<BPL>(a[K - 1], 2, L.s[wv + 1], lane);
+        if (lane < 32 && (lane & 15) == K - 1) L.es[wv + 1][lane >> 4] = Vec4<V>{e[2], e[3], e[6], e[7]};
+    }
+    if constexpr (!PH) return;
     if (lane == kLanes - 1) {
 #pragma unroll
         for (int r = 0; r < K; r += 2) {
@@ -620,9 +670,29 @@ __device__ __forceinline__ void scale(V (&a)[K][BX], V (&e)[8], float s0, float 
     e[0] *= s0; e[3] *= s3; e[4] *= s0; e[7] *= s3;
 }
 
+// Synchronisation before the horizontal factor of a step.  The separable
+// scheme takes a work-group barrier there, as the paper's separable lifting
+// does.  In the factored scheme the horizontal factor reads only values of
+// its own wave (DPP and the wave's own LDS exchange columns; a wave's LDS
+// accesses execute in program order), so no barrier is needed: the fused
+// step keeps its single barrier, before its vertical factor.
+template <int SCH>
+__device__ __forceinline__ void sync_horizontal() {
+    if constexpr (SCH == kSchemeSeparable) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // The step program of one scale.  Each "sync" is the single barrier of one
-// fused step; the LDS rows it guards are published just before it.
-template <int DIR, int WAV, bool EDGE, bool SPLIT, int NW, int BPL, int K, typename V>
+// step; the LDS rows it guards are published just before it.  SCH selects
+// the fused steps (4 barriers for CDF 9/7, 2 for 5/3), the fused steps with
+// the split, the separable steps (8 and 4 barriers), or the fused steps
+// evaluated as their horizontal and vertical factors (4 and 2 barriers).
+template <int DIR, int WAV, bool EDGE, int SCH, int NW, int BPL, int K, typename V>
 __device__ __forceinline__ void run(V (&a)[K][Lay<BPL>::BX], V (&e)[8], TileLds<V, NW, BPL, K>& L, int lane, int wv,
                                     const Geo& g, const TileGeo<BPL>& tg) {
     // the slots no wave publishes to hold zeros (the transposed border
@@ -641,11 +711,46 @@ __device__ __forceinline__ void run(V (&a)[K][Lay<BPL>::BX], V (&e)[8], TileLds<
     plus_step<KIND_, M_, EDGE, NW, BPL, K>(a, e, L, lane, wv, g, tg, (c_));
 #define DWT2_MINUS(KIND_, M_, c_) publish_minus<NW, BPL, K>(a, e, L, lane, wv); __syncthreads(); \
     minus_step<KIND_, M_, EDGE, NW, BPL, K>(a, e, L, lane, wv, g, tg, (c_));
+    // separable steps publish only what their axis reads: exchange columns
+    // (horizontal) or edge rows (vertical)
+#define DWT2_PH(KIND_, M_, c_) publish_plus<NW, BPL, K, true, false>(a, e, L, lane, wv); sync_horizontal<SCH>(); \
+    plus_step<KIND_, M_, EDGE, NW, BPL, K>(a, e, L, lane, wv, g, tg, (c_));
+#define DWT2_PV(KIND_, M_, c_) publish_plus<NW, BPL, K, false, true>(a, e, L, lane, wv); __syncthreads(); \
+    plus_step<KIND_, M_, EDGE, NW, BPL, K>(a, e, L, lane, wv, g, tg, (c_));
+#define DWT2_MH(KIND_, M_, c_) publish_minus<NW, BPL, K, true, false>(a, e, L, lane, wv); sync_horizontal<SCH>(); \
+    minus_step<KIND_, M_, EDGE, NW, BPL, K>(a, e, L, lane, wv, g, tg, (c_));
+#define DWT2_MV(KIND_, M_, c_) publish_minus<NW, BPL, K, false, true>(a, e, L, lane, wv); __syncthreads(); \
+    minus_step<KIND_, M_, EDGE, NW, BPL, K>(a, e, L, lane, wv, g, tg, (c_));
     // halo masks (first halo block = 1, second = 2) per step, from the column ranges each stage
     // must cover: predict/update/predict/update -> 3, 3, 2, 0;
     // update/predict/update/predict -> 3, 3, 1, 0; predict/update -> 2, 0;
-    // update/predict -> 1, 0
-    if constexpr (WAV == kCdf53) {
+    // update/predict -> 1, 0.  Separable: a vertical step keeps the mask of
+    // the horizontal step before it (forward 3,3,3,3,2,2,0,0; inverse
+    // 3,3,3,3,3,1,1,0; 5/3 forward 2,2,0,0; 5/3 inverse 3,1,1,0).
+    if constexpr (SCH == kSchemeSeparable || SCH == kSchemeFactored) {
+        static_assert(DIR != kAdjoint, "the separable and factored schemes have no adjoint");
+        if constexpr (WAV == kCdf53) {
+            if constexpr (DIR == kForward) {
+                DWT2_PH(kSepHInt, 2, 0.f) DWT2_PV(kSepVInt, 2, 0.f)
+                DWT2_MH(kSepHInt, 0, 0.f) DWT2_MV(kSepVInt, 0, 0.f)
+            } else {
+                DWT2_MV(kSepVIntInv, 3, 0.f) DWT2_MH(kSepHIntInv, 1, 0.f)
+                DWT2_PV(kSepVIntInv, 1, 0.f) DWT2_PH(kSepHIntInv, 0, 0.f)
+            }
+        } else if constexpr (DIR == kForward) {
+            DWT2_PH(kSepH, 3, kAlpha) DWT2_PV(kSepV, 3, kAlpha)
+            DWT2_MH(kSepH, 3, kBeta) DWT2_MV(kSepV, 3, kBeta)
+            DWT2_PH(kSepH, 2, kGamma) DWT2_PV(kSepV, 2, kGamma)
+            DWT2_MH(kSepH, 0, kDelta) DWT2_MV(kSepV, 0, kDelta)
+            scale(a, e, kZeta2, kZetaM2);
+        } else {
+            scale(a, e, kZetaM2, kZeta2);
+            DWT2_MV(kSepV, 3, -kDelta) DWT2_MH(kSepH, 3, -kDelta)
+            DWT2_PV(kSepV, 3, -kGamma) DWT2_PH(kSepH, 3, -kGamma)
+            DWT2_MV(kSepV, 3, -kBeta) DWT2_MH(kSepH, 1, -kBeta)
+            DWT2_PV(kSepV, 1, -kAlpha) DWT2_PH(kSepH, 0, -kAlpha)
+        }
+    } else if constexpr (WAV == kCdf53) {
         if constexpr (DIR == kForward) {
             DWT2_PLUS(kIntFwd, 2, 0.f)
             DWT2_MINUS(kIntFwd, 0, 0.f)
@@ -654,7 +759,7 @@ __device__ __forceinline__ void run(V (&a)[K][Lay<BPL>::BX], V (&e)[8], TileLds<
             DWT2_PLUS(kIntInv, 0, 0.f)
         }
     } else if constexpr (DIR == kForward) {
-        if constexpr (SPLIT) {
+        if constexpr (SCH == kSchemeSplit) {
             local_predict(a, e, kAlpha);
             DWT2_PLUS(kSplit, 3, kAlpha) local_update(a, e, kBeta);
             DWT2_MINUS(kSplit, 3, kBeta) local_predict(a, e, kGamma);
@@ -669,7 +774,7 @@ __device__ __forceinline__ void run(V (&a)[K][Lay<BPL>::BX], V (&e)[8], TileLds<
         scale(a, e, kZeta2, kZetaM2);
     } else if constexpr (DIR == kInverse) {
         scale(a, e, kZetaM2, kZeta2);
-        if constexpr (SPLIT) {
+        if constexpr (SCH == kSchemeSplit) {
             DWT2_MINUS(kSplit, 3, -kDelta) local_update(a, e, -kDelta);
             DWT2_PLUS(kSplit, 3, -kGamma) local_predict(a, e, -kGamma);
             DWT2_MINUS(kSplit, 1, -kBeta) local_update(a, e, -kBeta);
@@ -691,6 +796,10 @@ __device__ __forceinline__ void run(V (&a)[K][Lay<BPL>::BX], V (&e)[8], TileLds<
     }
 #undef DWT2_PLUS
 #undef DWT2_MINUS
+#undef DWT2_PH
+#undef DWT2_PV
+#undef DWT2_MH
+#undef DWT2_MV
 }
 
 // ---------------------------------------------------------------------------
@@ -1078,7 +1187,7 @@ __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::B
 
 // One tile (tx, ty) of one level: load, the fused steps, store.  The LDS
 // belongs to the calling work-group.
-template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K, int BPL>
+template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL>
 __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
                                           TileLds<typename St<T>::V, NW, BPL, K>& lds, int lane, int wv) {
     using V = typename St<T>::V;
@@ -1106,17 +1215,18 @@ __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
     V e[8];
     if (interior) {
         load_tile<DIR, T, false, BPL>(a, e, P, g, tg, lane);
-        run<DIR, WAV, false, SPLIT, NW, BPL>(a, e, lds, lane, wv, g, tg);
+        run<DIR, WAV, false, SCH, NW, BPL>(a, e, lds, lane, wv, g, tg);
         store_tile<DIR, T, false, NW, BPL>(a, P, g, wv);
     } else if constexpr (DIR != kAdjoint) {
         // border tile: symmetric extension at load time, unclamped steps
+        // (the split applies to interior tiles only)
         load_tile_mirror<DIR, T, BPL>(a, e, P, g, tg, lane);
-        run<DIR, WAV, false, false, NW, BPL>(a, e, lds, lane, wv, g, tg);
+        run<DIR, WAV, false, SCH == kSchemeSplit ? kSchemeFused : SCH, NW, BPL>(a, e, lds, lane, wv, g, tg);
         store_tile<DIR, T, true, NW, BPL>(a, P, g, wv);
     } else {
         // the adjoint's border weights are not a symmetric extension
         load_tile<DIR, T, true, BPL>(a, e, P, g, tg, lane);
-        run<DIR, WAV, true, false, NW, BPL>(a, e, lds, lane, wv, g, tg);
+        run<DIR, WAV, true, kSchemeFused, NW, BPL>(a, e, lds, lane, wv, g, tg);
         store_tile<DIR, T, true, NW, BPL>(a, P, g, wv);
     }
 }
@@ -1135,7 +1245,7 @@ __device__ __forceinline__ LevelParams plane_params(const LevelParams& P, int pl
     return Q;
 }
 
-template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K, int BPL>
+template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL>
 __global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
     using V = typename St<T>::V;
     __shared__ TileLds<V, NW, BPL, K> lds;
@@ -1158,7 +1268,7 @@ __global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
     const int t = g - pl * nt;
     const int ty = t / P.tiles_x;
     const int tx = t - ty * P.tiles_x;
-    tile_body<DIR, WAV, T, SPLIT, NW, K, BPL>(plane_params<T>(P, pl), tx, ty, lds, lane, wv);
+    tile_body<DIR, WAV, T, SCH, NW, K, BPL>(plane_params<T>(P, pl), tx, ty, lds, lane, wv);
 }
 
 // ===========================================================================

@@ -5,7 +5,7 @@
 namespace dwt2 {
 namespace kern {
 
-template <int DIR, int WAV, typename T, bool SPLIT, int NW, int K, int BPL>
+template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL>
 hipError_t launch_shape(const LevelParams& p, int planes, hipStream_t s) {
     // the tiles of all planes, rounded up to a multiple of 8 chunks of
     // kRemapRows tile rows (see level_kernel); planes beyond what one grid
@@ -25,7 +25,7 @@ hipError_t launch_shape(const LevelParams& p, int planes, hipStream_t s) {
             if (q.out_ll) q.out_ll = static_cast<T*>(q.out_ll) + p0 * q.out_ll_ps;
         }
         const int64_t grid = (nt * q.planes + 8 * chunk - 1) / (8 * chunk) * (8 * chunk);
-        hipLaunchKernelGGL((level_kernel<DIR, WAV, T, SPLIT, NW, K, BPL>), dim3((unsigned)grid),
+        hipLaunchKernelGGL((level_kernel<DIR, WAV, T, SCH, NW, K, BPL>), dim3((unsigned)grid),
                            dim3(NW * kLanes), 0, s, q);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -43,16 +43,20 @@ hipError_t launch_stream(const LevelParams& p, int planes, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int DIR, int WAV, typename T, bool SPLIT>
+template <int DIR, int WAV, typename T, int SCH>
 hipError_t launch(int cfg, const LevelParams& p, int planes, hipStream_t s) {
     static_assert(kNumConfigs == 8, "dispatch table below lists every kernel configuration");
+    // the streaming kernels implement the fused steps (with or without the split)
 #define DWT2_CFG(i)                                                                              \
     case i:                                                                                      \
         if constexpr (kConfigs[i].algo == kAlgoTile)                                             \
-            return launch_shape<DIR, WAV, T, SPLIT, kConfigs[i].waves, kConfigs[i].rows,         \
+            return launch_shape<DIR, WAV, T, SCH, kConfigs[i].waves, kConfigs[i].rows,           \
                                 kConfigs[i].bpl>(p, planes, s);                                  \
+        else if constexpr (SCH == kSchemeFused || SCH == kSchemeSplit)                           \
+            return launch_stream<DIR, WAV, T, SCH == kSchemeSplit, kConfigs[i].waves,            \
+                                 kConfigs[i].rows>(p, planes, s);                                \
         else                                                                                     \
-            return launch_stream<DIR, WAV, T, SPLIT, kConfigs[i].waves, kConfigs[i].rows>(p, planes, s);
+            return hipErrorInvalidValue;
     switch (cfg) {
         DWT2_CFG(0) DWT2_CFG(1) DWT2_CFG(2) DWT2_CFG(3) DWT2_CFG(4) DWT2_CFG(5) DWT2_CFG(6) DWT2_CFG(7)
     }
@@ -61,26 +65,39 @@ hipError_t launch(int cfg, const LevelParams& p, int planes, hipStream_t s) {
 }
 
 template <int DIR, typename T>
-hipError_t launch_float(bool split, int cfg, const LevelParams& p, int planes, hipStream_t s) {
+hipError_t launch_float(Scheme sch, int cfg, const LevelParams& p, int planes, hipStream_t s) {
     if constexpr (DIR == kAdjoint) {
-        return launch<DIR, kCdf97, T, false>(cfg, p, planes, s);
+        return sch == kSchemeFused ? launch<DIR, kCdf97, T, kSchemeFused>(cfg, p, planes, s) : hipErrorInvalidValue;
     } else {
-        return split ? launch<DIR, kCdf97, T, true>(cfg, p, planes, s)
-                     : launch<DIR, kCdf97, T, false>(cfg, p, planes, s);
+        switch (sch) {
+            case kSchemeFused: return launch<DIR, kCdf97, T, kSchemeFused>(cfg, p, planes, s);
+            case kSchemeSplit: return launch<DIR, kCdf97, T, kSchemeSplit>(cfg, p, planes, s);
+            case kSchemeSeparable: return launch<DIR, kCdf97, T, kSchemeSeparable>(cfg, p, planes, s);
+            case kSchemeFactored: return launch<DIR, kCdf97, T, kSchemeFactored>(cfg, p, planes, s);
+        }
+        return hipErrorInvalidValue;
     }
 }
 
 template <int DIR>
-hipError_t launch_dir(Wavelet wav, Dtype dt, bool split, int cfg, const LevelParams& p, int planes,
+hipError_t launch_dir(Wavelet wav, Dtype dt, Scheme sch, int cfg, const LevelParams& p, int planes,
                       hipStream_t s) {
     if (wav == kCdf53) {
-        if constexpr (DIR == kAdjoint) return hipErrorInvalidValue;
-        else return launch<DIR, kCdf53, int32_t, false>(cfg, p, planes, s);
+        if constexpr (DIR == kAdjoint) {
+            return hipErrorInvalidValue;
+        } else {
+            switch (sch) {
+                case kSchemeFused: return launch<DIR, kCdf53, int32_t, kSchemeFused>(cfg, p, planes, s);
+                case kSchemeSeparable: return launch<DIR, kCdf53, int32_t, kSchemeSeparable>(cfg, p, planes, s);
+                case kSchemeFactored: return launch<DIR, kCdf53, int32_t, kSchemeFactored>(cfg, p, planes, s);
+                default: return hipErrorInvalidValue;
+            }
+        }
     }
     switch (dt) {
-        case kF32: return launch_float<DIR, float>(split, cfg, p, planes, s);
-        case kBF16: return launch_float<DIR, __hip_bfloat16>(split, cfg, p, planes, s);
-        case kF16: return launch_float<DIR, __half>(split, cfg, p, planes, s);
+        case kF32: return launch_float<DIR, float>(sch, cfg, p, planes, s);
+        case kBF16: return launch_float<DIR, __hip_bfloat16>(sch, cfg, p, planes, s);
+        case kF16: return launch_float<DIR, __half>(sch, cfg, p, planes, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -77,7 +77,7 @@ def test_argument_errors(fn):
     assert call(fn, levels=7) == -3          # 64 x 64 allows 6
     assert call(fn, boundary=1) == -6
     assert call(fn, dtype=7) == -4
-    assert call(fn, flags=4) == -11
+    assert call(fn, flags=16) == -11
     # workspace required for 2 levels
     assert call(fn, levels=2) == -8
     assert call(fn, levels=2, ws=FAKE_WS, ws_n=10) == -8
@@ -98,6 +98,23 @@ def test_wavelet_dtype_pairs():
     # the split is a CDF 9/7 forward / inverse option
     assert call(dtype=d.DWT2_I32, wav=d.DWT2_CDF53_REV, flags=d.DWT2_FLAG_SPLIT) == -11
     assert call(d.dwt2_adj, flags=d.DWT2_FLAG_SPLIT) == -11
+
+
+def test_separable_flag_combinations():
+    # the separable comparison scheme: forward / inverse, both wavelets, tile
+    # configurations only, not together with the split, no adjoint
+    stream_cfg = next(i for i in range(d.DWT2_NUM_KERNEL_CONFIGS)
+                      if d.dwt2_kernel_config(i)[1] == d.DWT2_ALGO_STREAM)
+    for sep in (d.DWT2_FLAG_SEPARABLE, d.DWT2_FLAG_FACTORED):
+        for fn in (d.dwt2_fwd, d.dwt2_inv):
+            assert call(fn, flags=sep | d.DWT2_FLAG_SPLIT) == -11
+            assert call(fn, flags=sep | d.DWT2_FLAG_KERNEL(stream_cfg)) == -11
+            # valid combinations get past the flag checks (to the fake-pointer alias check)
+            assert call(fn, flags=sep, dst=FAKE_SRC + 4) == -9
+            assert call(fn, flags=sep | d.DWT2_FLAG_KERNEL(3), dst=FAKE_SRC + 4) == -9
+            assert call(fn, flags=sep, dtype=d.DWT2_I32, wav=d.DWT2_CDF53_REV, dst=FAKE_SRC + 4) == -9
+        assert call(d.dwt2_adj, flags=sep) == -11
+    assert call(flags=d.DWT2_FLAG_SEPARABLE | d.DWT2_FLAG_FACTORED) == -11
 
 
 def test_status_strings():
