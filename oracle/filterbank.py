@@ -60,9 +60,10 @@ def half_band_Q(N: int) -> np.ndarray:
 def cdf_filters(name: str):
     """(h, g): analysis low-pass h (centred on an even sample) and high-pass g
     (centred on an odd sample), normalised as the oracle's lifting form:
-    CDF 9/7 with DC gain sqrt(2) for both low-pass filters, CDF 5/3 (the real
-    counterpart of the reversible integer transform) with h DC gain 1 and
-    g = (-1/2, 1, -1/2)."""
+    CDF 9/7 with DC gain sqrt(2) for both low-pass filters, "cdf53" (the real
+    counterpart of the reversible integer transform, unscaled) with h DC gain
+    1 and g = (-1/2, 1, -1/2), and "cdf53f" (the real-valued CDF 5/3 with the
+    CDF 9/7 normalisation) with DC gain sqrt(2) for both low-pass filters."""
     if name == "cdf97":
         roots = npoly.polyroots(half_band_Q(4))
         real = [r for r in roots if abs(r.imag) < 1e-12]
@@ -73,12 +74,13 @@ def cdf_filters(name: str):
         h, f0 = h.real, f0.real
         h *= math.sqrt(2.0) / h.sum()
         f0 *= math.sqrt(2.0) / f0.sum()
-    elif name == "cdf53":
+    elif name in ("cdf53", "cdf53f"):
         q = half_band_Q(2)                      # 1 + 2y
         h = _lp_mul(_c_term(), q[0] * np.array([0, 1.0, 0]) + q[1] * _y_minus(0.0).real)
         f0 = _c_term().copy()
-        h *= 1.0 / h.sum()
-        f0 *= 2.0 / f0.sum()
+        gh, gf = (1.0, 2.0) if name == "cdf53" else (math.sqrt(2.0), math.sqrt(2.0))
+        h *= gh / h.sum()
+        f0 *= gf / f0.sum()
     else:
         raise ValueError(name)
     L = (len(f0) - 1) // 2

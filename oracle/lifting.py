@@ -48,6 +48,10 @@ Conventions fixed here (the paper leaves them open)
   high-pass output by 1/zeta along each axis, zeta chosen so that the low-pass
   filter has DC gain sqrt(2) (a constant image c gives LL = 2c per level).
   In 2-D: LL * zeta^2, HL * 1, LH * 1, HH * zeta^-2.
+* CDF 5/3 (real valued, as evaluated in the paper's Section "Evaluation"):
+  one pair, predict p = -1/2 and update u = 1/4, then the same scaling rule
+  as CDF 9/7 (low-pass DC gain sqrt(2) per axis), which here gives
+  zeta = sqrt(2): LL * 2, HH * 1/2.
 * Reversible integer CDF 5/3 (the paper's 5/3 is real valued; this integer
   form keeps its predict -1/2 and update 1/4 with floor rounding):
       odd[m]  -= floor((even[m] + even[m+1]) / 2)
@@ -74,8 +78,14 @@ DELTA = 0.443506852043971
 # Scaling so that the composed low-pass filter has DC gain sqrt(2): a constant
 # signal c becomes c * (1 + 2 beta (1 + 2 alpha)) after the lifting pairs.
 ZETA = math.sqrt(2.0) / (1.0 + 2.0 * BETA * (1.0 + 2.0 * ALPHA))
+# Real-valued CDF 5/3: one pair; the same rule gives zeta = sqrt(2) since
+# 1 + 2p = 0.
+P53 = -0.5
+U53 = 0.25
+ZETA53 = math.sqrt(2.0) / (1.0 + 2.0 * U53 * (1.0 + 2.0 * P53))
 
-WAVELETS = ("cdf97", "cdf53")
+# "cdf53" is the reversible integer transform, "cdf53f" the real-valued one
+WAVELETS = ("cdf97", "cdf53", "cdf53f")
 INT_LIMIT = 1 << 28
 
 
@@ -83,7 +93,18 @@ def lifting_pairs(wavelet: str):
     """(p, u) per lifting pair of the float wavelet (eq. (2), K pairs)."""
     if wavelet == "cdf97":
         return [(ALPHA, BETA), (GAMMA, DELTA)]
+    if wavelet == "cdf53f":
+        return [(P53, U53)]
     raise ValueError(f"no float lifting pairs for {wavelet!r}")
+
+
+def zeta(wavelet: str) -> float:
+    """Per-axis scaling of the float wavelet (low-pass * zeta, high-pass / zeta)."""
+    if wavelet == "cdf97":
+        return ZETA
+    if wavelet == "cdf53f":
+        return ZETA53
+    raise ValueError(f"no scaling for {wavelet!r}")
 
 
 def is_integer(wavelet: str) -> bool:
@@ -231,8 +252,9 @@ def fwd_level(X: np.ndarray, wavelet: str) -> np.ndarray:
         _forward_pair(x, p, u, integer)
     x0, x1, x2, x3 = x
     if not integer:
-        x0 *= ZETA * ZETA
-        x3 *= 1.0 / (ZETA * ZETA)
+        z = zeta(wavelet)
+        x0 *= z * z
+        x3 *= 1.0 / (z * z)
     return quadrants(x0, x1, x2, x3, h, w)
 
 
@@ -244,8 +266,9 @@ def inv_level(Y: np.ndarray, wavelet: str) -> np.ndarray:
     integer = is_integer(wavelet)
     x = list(unquadrants(Y))
     if not integer:
-        x[0] *= 1.0 / (ZETA * ZETA)
-        x[3] *= ZETA * ZETA
+        z = zeta(wavelet)
+        x[0] *= 1.0 / (z * z)
+        x[3] *= z * z
     for p, u in reversed(_pairs(wavelet)):
         _inverse_pair(x, p, u, integer)
     return merge(*x, h, w)

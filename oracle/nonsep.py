@@ -32,7 +32,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .lifting import ZETA, lifting_pairs, is_integer, quadrants, split
+from .lifting import lifting_pairs, is_integer, quadrants, split, zeta
 
 
 def nb(a: np.ndarray, dn: int, dm: int, shape) -> np.ndarray:
@@ -163,6 +163,7 @@ def nonsep_fwd_level(X: np.ndarray, wavelet: str = "cdf97", split_consts: bool =
             x = S_nonlocal(S_local(T_nonlocal(T_local(x, p), p), u), u)
         else:
             x = S_fused(T_fused(x, p), u)
-    x[0] = x[0] * ZETA ** 2
-    x[3] = x[3] * ZETA ** -2
+    z = zeta(wavelet)
+    x[0] = x[0] * z ** 2
+    x[3] = x[3] * z ** -2
     return quadrants(*x, h, w)

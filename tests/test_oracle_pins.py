@@ -30,8 +30,9 @@ def test_perfect_reconstruction(h):
         lv = lifting.max_levels(h, w)
         X = rng.random((h, w))
         for levels in sorted({1, lv}):
-            Y = lifting.fwd(X, "cdf97", levels)
-            assert np.abs(lifting.inv(Y, "cdf97", levels) - X).max() < 1e-13
+            for wav in ("cdf97", "cdf53f"):
+                Y = lifting.fwd(X, wav, levels)
+                assert np.abs(lifting.inv(Y, wav, levels) - X).max() < 1e-13
         Xi = rng.integers(-1000, 1000, (h, w))
         for levels in sorted({1, lv}):
             Yi = lifting.fwd(Xi, "cdf53", levels)
@@ -39,25 +40,30 @@ def test_perfect_reconstruction(h):
 
 
 # ---------------------------------------------------------------- P2 ------
-def test_lifting_equals_closed_form_filter_bank_1d_sizes():
+@pytest.mark.parametrize("wav", ["cdf97", "cdf53f"])
+def test_lifting_equals_closed_form_filter_bank_1d_sizes(wav):
     """One scale equals separable convolution with the closed-form filters on
     the symmetrically extended image, for every row/column length 2..39."""
     rng = np.random.default_rng(7)
     for n in range(2, 40):
         X = rng.random((2, n))
-        assert rel_err(lifting.fwd(X, "cdf97"), filterbank.separable_bank(X, "cdf97")) < 1e-13
+        assert rel_err(lifting.fwd(X, wav), filterbank.separable_bank(X, wav)) < 1e-13
         X = rng.random((n, 3))
-        assert rel_err(lifting.fwd(X, "cdf97"), filterbank.separable_bank(X, "cdf97")) < 1e-13
+        assert rel_err(lifting.fwd(X, wav), filterbank.separable_bank(X, wav)) < 1e-13
 
 
 @pytest.mark.parametrize("shape", [(2, 2), (3, 2), (5, 9), (8, 8), (9, 13), (16, 18), (23, 17)])
 def test_lifting_equals_nonseparable_convolution(shape):
     """Non-separable convolution N = N^V N^H with 9x9 / 9x7 / 7x9 / 7x7 2-D
-    kernels (Section "Proposed Schemes") gives the same values."""
+    kernels (Section "Proposed Schemes") gives the same values; for CDF 5/3
+    the kernels are 5x5 / 5x3 / 3x5 / 3x3."""
     X = np.random.default_rng(1).random(shape)
     Yn, shapes = filterbank.nonseparable_bank(X, "cdf97")
     assert shapes == {"LL": (9, 9), "HL": (9, 7), "LH": (7, 9), "HH": (7, 7)}
     assert rel_err(lifting.fwd(X, "cdf97"), Yn) < 1e-13
+    Yn, shapes = filterbank.nonseparable_bank(X, "cdf53f")
+    assert shapes == {"LL": (5, 5), "HL": (5, 3), "LH": (3, 5), "HH": (3, 3)}
+    assert rel_err(lifting.fwd(X, "cdf53f"), Yn) < 1e-13
 
 
 # ---------------------------------------------------------------- P3 ------
@@ -134,6 +140,10 @@ def test_constant_images():
                 assert np.abs(blk - c * 2 ** lv).max() < 1e-12
             else:
                 assert np.abs(blk).max() < 1e-12
+        Yf = lifting.fwd(X, "cdf53f", lv)
+        for l, b, r0, r1, c0, c1 in boxes:
+            blk = Yf[r0:r1, c0:c1]
+            assert np.abs(blk - (c * 2 ** lv if b == "LL" else 0.0)).max() < 1e-12
         Xi = np.full(shape, 77)
         Yi = lifting.fwd(Xi, "cdf53", lv)
         for l, b, r0, r1, c0, c1 in boxes:
@@ -155,6 +165,36 @@ def test_polynomial_images_cdf97():
     # a degree-4 term is not annihilated (the pin is sharp)
     Y4 = lifting.fwd(X + i ** 4, "cdf97", 1)
     assert np.abs(Y4[he + m:H - m, m:we - m]).max() > 1e-9
+
+
+def test_linear_images_cdf53f():
+    """Real CDF 5/3 (2 vanishing moments): images of degree <= 1 in each axis
+    have zero details away from borders; a quadratic term is not annihilated."""
+    H, W = 40, 46
+    i = np.arange(H)[:, None] / H
+    j = np.arange(W)[None, :] / W
+    X = 0.3 + 1.7 * i - 0.9 * j + 2.5 * i * j
+    Y = lifting.fwd(X, "cdf53f", 1)
+    he, we = H // 2, W // 2
+    m = 2
+    for blk in (Y[m:he - m, we + m:W - m], Y[he + m:H - m, m:we - m], Y[he + m:H - m, we + m:W - m]):
+        assert np.abs(blk).max() < 1e-13
+    # LL away from the border: the image at even samples, times zeta^2 = 2,
+    # plus the update's zero contribution
+    assert np.abs(Y[m:he - m, m:we - m] - 2 * X[0::2, 0::2][m:he - m, m:we - m]).max() < 1e-13
+    Y2 = lifting.fwd(X + i ** 2, "cdf53f", 1)
+    assert np.abs(Y2[he + m:H - m, m:we - m]).max() > 1e-6
+
+
+def test_real_53_constants_and_filters():
+    """p = -1/2, u = 1/4, zeta = sqrt(2): the closed-form 5/3 pair with the
+    CDF 9/7 normalisation (both low-pass filters of DC gain sqrt(2))."""
+    h, g = filterbank.cdf_filters("cdf53f")
+    r2 = math.sqrt(2.0)
+    assert np.abs(h - r2 * np.array([-1, 2, 6, 2, -1]) / 8).max() < 1e-15
+    assert np.abs(g - np.array([-1, 2, -1]) / (2 * r2)).max() < 1e-15
+    assert lifting.lifting_pairs("cdf53f") == [(-0.5, 0.25)]
+    assert abs(lifting.zeta("cdf53f") - r2) < 1e-15
 
 
 def test_bilinear_integer_images_cdf53():
@@ -218,6 +258,9 @@ def test_separable_equals_nonseparable(shape):
     assert rel_err(nonsep.nonsep_fwd_level(X, "cdf97", split_consts=True), ref) < 1e-14
     Xi = rng.integers(-300, 300, shape)
     assert np.array_equal(nonsep.nonsep_fwd_level(Xi, "cdf53"), lifting.fwd(Xi, "cdf53", 1))
+    ref = lifting.fwd(X, "cdf53f", 1)
+    assert rel_err(nonsep.nonsep_fwd_level(X, "cdf53f"), ref) < 1e-14
+    assert rel_err(nonsep.nonsep_fwd_level(X, "cdf53f", split_consts=True), ref) < 1e-14
 
 
 def test_separable_equals_nonseparable_int_all_small_shapes():
@@ -343,11 +386,11 @@ def test_multilevel_is_recursive_on_ll():
 
 
 # ---------------------------------------------------------------- window --
-@pytest.mark.parametrize("wav,levels", [("cdf97", 3), ("cdf53", 2), ("cdf97", 1)])
+@pytest.mark.parametrize("wav,levels", [("cdf97", 3), ("cdf53", 2), ("cdf97", 1), ("cdf53f", 3)])
 def test_crop_window_matches_full_oracle(wav, levels):
     H, W = 352, 416
     rng = np.random.default_rng(8)
-    X = rng.random((H, W)) if wav == "cdf97" else rng.integers(0, 256, (H, W))
+    X = rng.integers(0, 256, (H, W)) if wav == "cdf53" else rng.random((H, W))
     Y = lifting.fwd(X, wav, levels)
     for r0, r1, c0, c1 in window.probe_crops(H, W, levels, size=64):
         sub = lifting.fwd(X[r0:r1, c0:c1], wav, levels)
