@@ -13,7 +13,7 @@ written once = 2 * 4 B/px) and a `cpu_baseline` object (the CPU oracle timed
 on a bounded crop of the same image).  `forms` lists the other forms of the
 path, measured the same way with fewer steps: 5 levels, the P0/P1 split,
 inverse, the separable comparison scheme (twice the steps and barriers),
-BF16 / FP16 storage, reversible 5/3, warm and gradient-input
+the factored fused steps, real CDF 5/3, BF16 / FP16 storage, reversible 5/3, warm and gradient-input
 variants, 1024^2 (per call and under graph replay), 4096^2 (cold and warm)
 and 16384^2 images, 3 x 8192^2 planes forward + inverse at each storage type
 with coefficient error and reconstruction PSNR, the autograd training step
@@ -221,6 +221,11 @@ def main():
              lambda i, c: d.inv(ys[i % pairs], "cdf97", 1, out=xs[i % pairs], config=c, separable=True), 1, 4)
         form("cdf97 fwd f32 5 levels separable (8 barriers)",
              lambda i, c: d.fwd(xs[i % pairs], "cdf97", 5, out=ys[i % pairs], config=c, separable=True), 5, 4)
+        # the real-valued CDF 5/3 (one fused predict + update, 2 barriers)
+        form("cdf53 real fwd f32 1 level",
+             lambda i, c: d.fwd(xs[i % pairs], "cdf53f", 1, out=ys[i % pairs], config=c), 1, 4)
+        form("cdf53 real inv f32 1 level",
+             lambda i, c: d.inv(ys[i % pairs], "cdf53f", 1, out=xs[i % pairs], config=c), 1, 4)
         # the fused steps evaluated as their two 1-D factors (4 barriers)
         form("cdf97 fwd f32 1 level factored (4 barriers)",
              lambda i, c: d.fwd(xs[i % pairs], "cdf97", 1, out=ys[i % pairs], config=c, factored=True), 1, 4)

@@ -72,7 +72,10 @@ typedef enum {
 
 typedef enum {
     DWT2_CDF97 = 0,         /* CDF 9/7, float storage (F32, BF16, F16)          */
-    DWT2_CDF53_REV = 1      /* reversible integer CDF 5/3, I32 storage only     */
+    DWT2_CDF53_REV = 1,     /* reversible integer CDF 5/3, I32 storage only     */
+    DWT2_CDF53 = 2          /* real-valued CDF 5/3 (the paper's 5/3, Section
+                               "Evaluation"), float storage; p = -1/2,
+                               u = 1/4, LL * 2, HH * 1/2 (zeta = sqrt(2))    */
 } dwt2_wavelet;
 
 typedef enum {

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libdwt2.so")
 # enums of include/dwt2.h
 DWT2_OK = 0
 DWT2_E_HIP = -10
-DWT2_CDF97, DWT2_CDF53_REV = 0, 1
+DWT2_CDF97, DWT2_CDF53_REV, DWT2_CDF53 = 0, 1, 2
 DWT2_F32, DWT2_BF16, DWT2_F16, DWT2_I32 = 0, 1, 2, 3
 DWT2_SYMMETRIC_WHOLE = 0
 DWT2_FLAG_SPLIT = 1
@@ -38,7 +38,8 @@ def DWT2_FLAG_KERNEL(i: int) -> int:
     return (i + 1) << DWT2_FLAG_KERNEL_SHIFT
 
 
-WAVELETS = {"cdf97": DWT2_CDF97, "cdf53": DWT2_CDF53_REV}
+# "cdf53": the reversible integer CDF 5/3; "cdf53f": the real-valued one
+WAVELETS = {"cdf97": DWT2_CDF97, "cdf53": DWT2_CDF53_REV, "cdf53f": DWT2_CDF53}
 
 # every function the header declares, with its ctypes signature
 _c_int, _c_i32, _c_i64, _c_u, _c_sz, _c_p = (ctypes.c_int, ctypes.c_int32, ctypes.c_int64,

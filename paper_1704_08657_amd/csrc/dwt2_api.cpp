@@ -119,7 +119,7 @@ int validate(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dp
              const void* ws, size_t ws_bytes, bool adjoint) {
     if (!src || !dst) return DWT2_E_NULL;
     if (planes < 1) return DWT2_E_COUNT;
-    if (wavelet != DWT2_CDF97 && wavelet != DWT2_CDF53_REV) return DWT2_E_WAVELET;
+    if (wavelet != DWT2_CDF97 && wavelet != DWT2_CDF53_REV && wavelet != DWT2_CDF53) return DWT2_E_WAVELET;
     if (dtype != DWT2_F32 && dtype != DWT2_BF16 && dtype != DWT2_F16 && dtype != DWT2_I32)
         return DWT2_E_DTYPE;
     if ((wavelet == DWT2_CDF53_REV) != (dtype == DWT2_I32)) return DWT2_E_DTYPE;
@@ -128,7 +128,7 @@ int validate(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dp
         return DWT2_E_FLAGS;
     if (((flags & DWT2_FLAG_KERNEL_MASK) >> DWT2_FLAG_KERNEL_SHIFT) > (unsigned)dwt2::kNumConfigs)
         return DWT2_E_FLAGS;
-    if ((flags & DWT2_FLAG_SPLIT) && (wavelet != DWT2_CDF97 || adjoint)) return DWT2_E_FLAGS;
+    if ((flags & DWT2_FLAG_SPLIT) && (wavelet == DWT2_CDF53_REV || adjoint)) return DWT2_E_FLAGS;
     // at most one scheme flag; the separable and factored schemes: forward /
     // inverse on tile configurations
     const unsigned schemes = flags & (DWT2_FLAG_SPLIT | DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED);
@@ -163,7 +163,9 @@ int report(hipError_t e) {
 }
 
 dwt2::Dtype to_dtype(int d) { return (dwt2::Dtype)d; }
-dwt2::Wavelet to_wav(int w) { return w == DWT2_CDF97 ? dwt2::kCdf97 : dwt2::kCdf53; }
+dwt2::Wavelet to_wav(int w) {
+    return w == DWT2_CDF97 ? dwt2::kCdf97 : w == DWT2_CDF53 ? dwt2::kCdf53Real : dwt2::kCdf53;
+}
 
 // Work-group grid of one level for kernel configuration `cfg`.
 void plan_grid(int cfg, dwt2::LevelParams* lp) {
@@ -413,7 +415,6 @@ int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_ima
                      unsigned flags, void* workspace, size_t workspace_bytes, void* stream) {
     if (!host_images || !device_images || !workspace) return DWT2_E_NULL;
     if (count < 1) return DWT2_E_COUNT;
-    if (wavelet != DWT2_CDF97 && wavelet != DWT2_CDF53_REV) return DWT2_E_WAVELET;
     if (wavelet != DWT2_CDF97) return DWT2_E_WAVELET;        // batched path: CDF 9/7
     if (dtype != DWT2_F32 && dtype != DWT2_BF16 && dtype != DWT2_F16) return DWT2_E_DTYPE;
     if (boundary != DWT2_SYMMETRIC_WHOLE) return DWT2_E_BOUNDARY;

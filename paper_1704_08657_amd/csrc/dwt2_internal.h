@@ -10,7 +10,8 @@
 namespace dwt2 {
 
 enum Direction : int { kForward = 0, kInverse = 1, kAdjoint = 2 };
-enum Wavelet : int { kCdf97 = 0, kCdf53 = 1 };
+// kCdf53: the reversible integer CDF 5/3; kCdf53Real: the real-valued one
+enum Wavelet : int { kCdf97 = 0, kCdf53 = 1, kCdf53Real = 2 };
 enum Dtype : int { kF32 = 0, kBF16 = 1, kF16 = 2, kI32 = 3 };
 // Lifting scheme of a level: the fused non-separable steps, the fused steps
 // with the P0/P1 split, the separable steps (the comparison scheme: every

@@ -55,6 +55,12 @@ constexpr float kDelta = 0.443506852043971f;
 constexpr double kZeta = 1.1496043988602418;
 constexpr float kZeta2 = (float)(kZeta * kZeta);
 constexpr float kZetaM2 = (float)(1.0 / (kZeta * kZeta));
+// Real-valued CDF 5/3: one pair, predict -1/2, update 1/4; the same
+// normalisation gives zeta = sqrt(2): LL * 2, HH * 1/2 (exact in FP32).
+constexpr float kP53 = -0.5f;
+constexpr float kU53 = 0.25f;
+constexpr float kZeta53Sq = 2.0f;
+constexpr float kZeta53SqInv = 0.5f;
 
 
 // ---------------------------------------------------------------------------
@@ -737,6 +743,16 @@ __device__ __forceinline__ void run(V (&a)[K][Lay<BPL>::BX], V (&e)[8], TileLds<
                 DWT2_MV(kSepVIntInv, 3, 0.f) DWT2_MH(kSepHIntInv, 1, 0.f)
                 DWT2_PV(kSepVIntInv, 1, 0.f) DWT2_PH(kSepHIntInv, 0, 0.f)
             }
+        } else if constexpr (WAV == kCdf53Real) {
+            if constexpr (DIR == kForward) {
+                DWT2_PH(kSepH, 2, kP53) DWT2_PV(kSepV, 2, kP53)
+                DWT2_MH(kSepH, 0, kU53) DWT2_MV(kSepV, 0, kU53)
+                scale(a, e, kZeta53Sq, kZeta53SqInv);
+            } else {
+                scale(a, e, kZeta53SqInv, kZeta53Sq);
+                DWT2_MV(kSepV, 3, -kU53) DWT2_MH(kSepH, 1, -kU53)
+                DWT2_PV(kSepV, 1, -kP53) DWT2_PH(kSepH, 0, -kP53)
+            }
         } else if constexpr (DIR == kForward) {
             DWT2_PH(kSepH, 3, kAlpha) DWT2_PV(kSepV, 3, kAlpha)
             DWT2_MH(kSepH, 3, kBeta) DWT2_MV(kSepV, 3, kBeta)
@@ -757,6 +773,28 @@ __device__ __forceinline__ void run(V (&a)[K][Lay<BPL>::BX], V (&e)[8], TileLds<
         } else {
             DWT2_MINUS(kIntInv, 1, 0.f)
             DWT2_PLUS(kIntInv, 0, 0.f)
+        }
+    } else if constexpr (WAV == kCdf53Real) {
+        static_assert(DIR != kAdjoint, "the adjoint is implemented for CDF 9/7");
+        if constexpr (DIR == kForward) {
+            if constexpr (SCH == kSchemeSplit) {
+                local_predict(a, e, kP53);
+                DWT2_PLUS(kSplit, 2, kP53) local_update(a, e, kU53);
+                DWT2_MINUS(kSplit, 0, kU53)
+            } else {
+                DWT2_PLUS(kFloat, 2, kP53)
+                DWT2_MINUS(kFloat, 0, kU53)
+            }
+            scale(a, e, kZeta53Sq, kZeta53SqInv);
+        } else {
+            scale(a, e, kZeta53SqInv, kZeta53Sq);
+            if constexpr (SCH == kSchemeSplit) {
+                DWT2_MINUS(kSplit, 1, -kU53) local_update(a, e, -kU53);
+                DWT2_PLUS(kSplit, 0, -kP53) local_predict(a, e, -kP53);
+            } else {
+                DWT2_MINUS(kFloat, 1, -kU53)
+                DWT2_PLUS(kFloat, 0, -kP53)
+            }
         }
     } else if constexpr (DIR == kForward) {
         if constexpr (SCH == kSchemeSplit) {
@@ -1337,6 +1375,30 @@ template <bool SPLIT> struct Prog<kAdjoint, kCdf97, SPLIT> {
     static constexpr float kPreLocalC = 0.f;
     static constexpr bool kPreScale = true;
     static constexpr float kPre0 = kZeta2, kPre3 = kZetaM2;
+    static constexpr bool kPostScale = false;
+    static constexpr float kPost0 = 1.f, kPost3 = 1.f;
+};
+template <bool SPLIT> struct Prog<kForward, kCdf53Real, SPLIT> {
+    static constexpr int N = 2;
+    static constexpr StepSpec kSteps[N] = {
+        {true, SPLIT ? kSplit : kFloat, kP53, SPLIT ? 2 : 0, kU53},
+        {false, SPLIT ? kSplit : kFloat, kU53, 0, 0.f}};
+    static constexpr int kPreLocal = SPLIT ? 1 : 0;
+    static constexpr float kPreLocalC = kP53;
+    static constexpr bool kPreScale = false;
+    static constexpr float kPre0 = 1.f, kPre3 = 1.f;
+    static constexpr bool kPostScale = true;
+    static constexpr float kPost0 = kZeta53Sq, kPost3 = kZeta53SqInv;
+};
+template <bool SPLIT> struct Prog<kInverse, kCdf53Real, SPLIT> {
+    static constexpr int N = 2;
+    static constexpr StepSpec kSteps[N] = {
+        {false, SPLIT ? kSplit : kFloat, -kU53, SPLIT ? 2 : 0, -kU53},
+        {true, SPLIT ? kSplit : kFloat, -kP53, SPLIT ? 1 : 0, -kP53}};
+    static constexpr int kPreLocal = 0;
+    static constexpr float kPreLocalC = 0.f;
+    static constexpr bool kPreScale = true;
+    static constexpr float kPre0 = kZeta53SqInv, kPre3 = kZeta53Sq;
     static constexpr bool kPostScale = false;
     static constexpr float kPost0 = 1.f, kPost3 = 1.f;
 };

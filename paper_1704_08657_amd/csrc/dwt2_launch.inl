@@ -64,18 +64,31 @@ hipError_t launch(int cfg, const LevelParams& p, int planes, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
-template <int DIR, typename T>
+template <int DIR, int WAV, typename T>
 hipError_t launch_float(Scheme sch, int cfg, const LevelParams& p, int planes, hipStream_t s) {
     if constexpr (DIR == kAdjoint) {
-        return sch == kSchemeFused ? launch<DIR, kCdf97, T, kSchemeFused>(cfg, p, planes, s) : hipErrorInvalidValue;
+        if constexpr (WAV == kCdf97)
+            return sch == kSchemeFused ? launch<DIR, WAV, T, kSchemeFused>(cfg, p, planes, s) : hipErrorInvalidValue;
+        else
+            return hipErrorInvalidValue;          // the adjoint is implemented for CDF 9/7
     } else {
         switch (sch) {
-            case kSchemeFused: return launch<DIR, kCdf97, T, kSchemeFused>(cfg, p, planes, s);
-            case kSchemeSplit: return launch<DIR, kCdf97, T, kSchemeSplit>(cfg, p, planes, s);
-            case kSchemeSeparable: return launch<DIR, kCdf97, T, kSchemeSeparable>(cfg, p, planes, s);
-            case kSchemeFactored: return launch<DIR, kCdf97, T, kSchemeFactored>(cfg, p, planes, s);
+            case kSchemeFused: return launch<DIR, WAV, T, kSchemeFused>(cfg, p, planes, s);
+            case kSchemeSplit: return launch<DIR, WAV, T, kSchemeSplit>(cfg, p, planes, s);
+            case kSchemeSeparable: return launch<DIR, WAV, T, kSchemeSeparable>(cfg, p, planes, s);
+            case kSchemeFactored: return launch<DIR, WAV, T, kSchemeFactored>(cfg, p, planes, s);
         }
         return hipErrorInvalidValue;
+    }
+}
+
+template <int DIR, int WAV>
+hipError_t launch_float_dtype(Dtype dt, Scheme sch, int cfg, const LevelParams& p, int planes, hipStream_t s) {
+    switch (dt) {
+        case kF32: return launch_float<DIR, WAV, float>(sch, cfg, p, planes, s);
+        case kBF16: return launch_float<DIR, WAV, __hip_bfloat16>(sch, cfg, p, planes, s);
+        case kF16: return launch_float<DIR, WAV, __half>(sch, cfg, p, planes, s);
+        default: return hipErrorInvalidValue;
     }
 }
 
@@ -94,12 +107,11 @@ hipError_t launch_dir(Wavelet wav, Dtype dt, Scheme sch, int cfg, const LevelPar
             }
         }
     }
-    switch (dt) {
-        case kF32: return launch_float<DIR, float>(sch, cfg, p, planes, s);
-        case kBF16: return launch_float<DIR, __hip_bfloat16>(sch, cfg, p, planes, s);
-        case kF16: return launch_float<DIR, __half>(sch, cfg, p, planes, s);
-        default: return hipErrorInvalidValue;
+    if (wav == kCdf53Real) {
+        if constexpr (DIR == kAdjoint) return hipErrorInvalidValue;
+        else return launch_float_dtype<DIR, kCdf53Real>(dt, sch, cfg, p, planes, s);
     }
+    return launch_float_dtype<DIR, kCdf97>(dt, sch, cfg, p, planes, s);
 }
 
 }  // namespace kern

@@ -93,6 +93,11 @@ def test_wavelet_dtype_pairs():
     assert call(dtype=d.DWT2_F32, wav=d.DWT2_CDF53_REV) == -4
     assert call(dtype=d.DWT2_BF16, wav=d.DWT2_CDF53_REV) == -4
     assert call(wav=5) == -5
+    # the real-valued CDF 5/3 takes float storage, has no adjoint, allows the split
+    assert call(dtype=d.DWT2_I32, wav=d.DWT2_CDF53) == -4
+    assert call(d.dwt2_adj, wav=d.DWT2_CDF53) == -5
+    for dt in (d.DWT2_F32, d.DWT2_BF16, d.DWT2_F16):
+        assert call(wav=d.DWT2_CDF53, dtype=dt, flags=d.DWT2_FLAG_SPLIT, dst=FAKE_SRC + 4) == -9
     # the adjoint is defined for the linear CDF 9/7 only
     assert call(d.dwt2_adj, dtype=d.DWT2_I32, wav=d.DWT2_CDF53_REV) == -5
     # the split is a CDF 9/7 forward / inverse option

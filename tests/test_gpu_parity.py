@@ -223,7 +223,8 @@ def test_kernel_configs_bit_identical():
     cases = [("cdf97", torch.float32, (517, 1283), 3, False), ("cdf97", torch.float32, (1000, 700), 1, True),
              ("cdf97", torch.bfloat16, (300, 260), 2, False), ("cdf53", torch.int32, (613, 901), 4, False),
              ("cdf97", torch.float32, (600, 2056), 2, False), ("cdf97", torch.float32, (600, 2056), 1, True),
-             ("cdf97", torch.bfloat16, (260, 2056), 1, False), ("cdf53", torch.int32, (520, 2056), 2, False)]
+             ("cdf97", torch.bfloat16, (260, 2056), 1, False), ("cdf53", torch.int32, (520, 2056), 2, False),
+             ("cdf53f", torch.float32, (517, 1283), 3, False), ("cdf53f", torch.float32, (600, 2056), 2, False)]
     for wav, tdt, (h, w), lv, split in cases:
         if wav == "cdf53":
             x = gpu(workloads.pixels_u8(h, w, seed=4))
