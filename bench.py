@@ -65,8 +65,10 @@ def measured_traffic():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    # about 0.2 s of warmup brings the GPU to its steady clocks (20 steps
+    # read about 1% slower); 1000 timed steps take about 0.1 s
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--no-forms", action="store_true", help="skip the secondary forms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
