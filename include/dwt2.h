@@ -13,7 +13,11 @@
  *     S_U : x0 += U x1 + U* x2 + U U* x3, x1 += U* x3, x2 += U x3
  * with one work-group barrier per step.  With DWT2_FLAG_SPLIT the constant
  * parts P0, U0 run as barrier-free separable lifting and only P1, U1 stay in
- * the fused step (Section "Optimization Approach").
+ * the fused step (Section "Optimization Approach").  DWT2_FLAG_SEPARABLE runs
+ * the separable lifting scheme the paper compares with (one barrier per 1-D
+ * step), DWT2_FLAG_FACTORED the fused steps evaluated as their 1-D factors.
+ * Wavelets: CDF 9/7 and the real-valued CDF 5/3 (float storage), and the
+ * reversible integer CDF 5/3.
  *
  * Conventions (the paper leaves them open; the library fixes them):
  *   - Output layout: Mallat pyramid in an H x W array.  Level l transforms the

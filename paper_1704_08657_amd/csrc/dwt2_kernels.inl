@@ -27,10 +27,14 @@
 //     one for each step shape, so one barrier per step suffices);
 //   * loads are 4-pixel vectors per image row, stores are BPL-sample vectors
 //     per subband row, both coalesced across the wave;
-//   * tiles touching the image border take a path that clamps neighbour
-//     indices into each component's extent (whole-point symmetric extension)
-//     or, for the adjoint, applies the transposed border weights; interior
-//     tiles take a branch-free path;
+//   * tiles touching the image border load the whole-point symmetric
+//     extension of the image and then run the same unclamped steps (each
+//     step keeps the extension symmetric); the adjoint's border tiles apply
+//     the transposed border weights instead; interior tiles take a
+//     branch-free vector path;
+//   * the step program is chosen at compile time: the fused steps, the fused
+//     steps with the split, the separable steps (the comparison scheme) or
+//     the fused steps evaluated as their two 1-D factors;
 //   * the tile index is remapped so that each XCD (work-groups are dealt
 //     round-robin over the 8 XCDs) takes whole rows of tiles, so the halo
 //     re-reads of neighbouring tiles hit that XCD's L2.
