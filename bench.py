@@ -26,6 +26,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -76,6 +77,8 @@ def parse():
                     help="time every kernel configuration on this GPU first and use the fastest, instead of the "
                          "committed autotuner cache (tuned_configs.json)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--only", default=None, metavar="REGEX",
+                    help="run only the forms whose name matches REGEX (the headline always runs)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="accepted for older profiling commands; the plain copy always runs")
     return ap.parse_args()
@@ -130,12 +133,54 @@ def cpu_baseline(x, seconds):
                       f"image, FP64 NumPy, single thread, {el:.1f} s"}
 
 
+def _pool_job(job):
+    """One oracle transform in a worker process: (pixels, seconds)."""
+    h, w, seed, levels = job
+    from oracle import lifting
+    import workloads
+    x = workloads.uniform(h, w, seed=seed)
+    t0 = time.perf_counter()
+    lifting.fwd(x, "cdf97", levels)
+    return h * w, time.perf_counter() - t0
+
+
+def cpu_pool_baseline():
+    """The CPU oracle over images of the batched and multi-plane workloads in a
+    pool of worker processes (one image per task), on bounded samples: the
+    first 24 images of the 256-image uneven batch (5 levels) and the 192
+    planes of 1024^2 of the differentiation workload (3 levels).  Run before
+    the GPU is initialised; workers = min(16, CPU count)."""
+    import multiprocessing as mp
+    import workloads
+    workers = max(1, min(16, os.cpu_count() or 1))
+    out = {}
+    samples = {
+        "batched: 24 of the 256 uneven images 64..4096, 5 levels":
+            [(h, w, 100 + k, 5) for k, (h, w) in enumerate(workloads.uneven_shapes(256, 64, 4096, seed=1)[:24])],
+        "planes: 192 x 1024^2 (64 x 3), 3 levels": [(1024, 1024, 200 + k, 3) for k in range(192)],
+    }
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        for name, jobs in samples.items():
+            t0 = time.perf_counter()
+            res = pool.map(_pool_job, jobs, chunksize=1)
+            el = time.perf_counter() - t0
+            px = sum(r[0] for r in res)
+            out[name] = {"value": px / el / 1e9, "unit": "Gpixel/s", "seconds": round(el, 2),
+                         "pixels": px, "busy_seconds": round(sum(r[1] for r in res), 2)}
+    return {"cores": workers, "kind": "oracle", "method": "multiprocessing pool, one image per task, "
+            "FP64 NumPy; wall time includes generating each input in its worker", "samples": out}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(this build has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
+    # the CPU pool runs before anything touches the GPU (its workers are forked)
+    pool = None if args.no_cpu else cpu_pool_baseline()
+
     import torch
     import paper_1704_08657_amd as d
     import workloads
@@ -196,8 +241,14 @@ def main():
     roofline["of_copy"] = round(achieved / copy_ref["GB/s"], 4)
 
     forms = []
+
+    def want(name):
+        return args.only is None or re.search(args.only, name) is not None
+
     if not args.no_forms:
         def form(name, fn, levels, elem, steps=50, tune_key=None):
+            if not want(name):
+                return
             if tune_key is not None:
                 tune(name, *tune_key, levels, lambda c, i: fn(i, c))
             tot, pr = time_steps(torch, lambda i: fn(i, None), steps, 5)
@@ -268,6 +319,8 @@ def main():
             input/output pairs (cold when they total >= 1 GiB; warm with one
             pair).  graph_calls > 0: also time one captured graph replaying
             that many calls (per-call time = replay time / graph_calls)."""
+            if not want(name):
+                return
             g = torch.Generator(device=dev).manual_seed(7)
             xn = [torch.rand((n, n), device=dev, generator=g) for _ in range(npairs)]
             yn = [torch.empty_like(t) for t in xn]
@@ -315,9 +368,13 @@ def main():
         # (which the parity tests hold within 1e-5 of the FP64 oracle) and,
         # for the reconstruction, against the rounded input and the FP32
         # original (PSNR with peak 1.0).
-        x3 = torch.from_numpy(workloads.planes(3, N, N, seed=3)).to(dev)
+        x3 = (torch.from_numpy(workloads.planes(3, N, N, seed=3)).to(dev)
+              if any(want(f"cdf97 fwd+inv {nm} 5 levels, 3 x {N}^2 planes") for nm in ("f32", "bf16", "f16"))
+              else None)
         c32 = None
         for tdt, nm in [(torch.float32, "f32"), (torch.bfloat16, "bf16"), (torch.float16, "f16")]:
+            if not want(f"cdf97 fwd+inv {nm} 5 levels, 3 x {N}^2 planes"):
+                continue
             xq = x3.to(tdt)
             cq = torch.empty_like(xq)
             rq = torch.empty_like(xq)
@@ -353,9 +410,12 @@ def main():
         # differentiation: 64 x 3 x 1024^2 FP32 (seed 4), 3-level forward via
         # the autograd function, loss = sum |details| + MSE(LL_3, target (seed
         # 5)), backward through the hand-written adjoint
-        xa = torch.from_numpy(workloads.planes(64 * 3, 1024, 1024, seed=4).reshape(64, 3, 1024, 1024)).to(dev)
-        xa.requires_grad_(True)
-        tgt = torch.from_numpy(workloads.planes(64 * 3, 128, 128, seed=5).reshape(64, 3, 128, 128)).to(dev)
+        ag_name = "autograd: 64 x 3 x 1024^2 FP32, 3-level forward + loss + adjoint backward"
+        xa = tgt = None
+        if want(ag_name):
+            xa = torch.from_numpy(workloads.planes(64 * 3, 1024, 1024, seed=4).reshape(64, 3, 1024, 1024)).to(dev)
+            xa.requires_grad_(True)
+            tgt = torch.from_numpy(workloads.planes(64 * 3, 128, 128, seed=5).reshape(64, 3, 128, 128)).to(dev)
 
         def train_step(i):
             y = d.dwt2(xa, 3)
@@ -363,17 +423,20 @@ def main():
             loss = y.abs().sum() - ll.abs().sum() + ((ll - tgt) ** 2).mean()
             loss.backward()
             xa.grad = None
-        _, pr = time_steps(torch, train_step, 10, 2)
-        ms = float(np.median(pr))
-        ab = 2 * 64 * 3 * algorithmic_bytes(1024, 1024, 3, 4)
-        forms.append({"form": "autograd: 64 x 3 x 1024^2 FP32, 3-level forward + loss + adjoint backward",
-                      "Gpixel/s": round(64 * 3 * 1024 * 1024 / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
-                      "transform_GB/s": round(ab / (ms * 1e-3) / 1e9, 1)})
+        if want(ag_name):
+            _, pr = time_steps(torch, train_step, 10, 2)
+            ms = float(np.median(pr))
+            ab = 2 * 64 * 3 * algorithmic_bytes(1024, 1024, 3, 4)
+            forms.append({"form": ag_name,
+                          "Gpixel/s": round(64 * 3 * 1024 * 1024 / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
+                          "transform_GB/s": round(ab / (ms * 1e-3) / 1e9, 1)})
         del xa, tgt
         torch.cuda.empty_cache()
 
         # batched, a planner launch plus one launch per level: 256 images with H, W uniform in [64, 4096] (even), 5 levels
         def batched_form(name, shapes, seed, steps=5):
+            if not want(name):
+                return
             g = torch.Generator(device=dev).manual_seed(seed)
             imgs = [torch.rand(s, device=dev, generator=g) for s in shapes]
             call = d.BatchedForward(imgs, 5)
@@ -406,19 +469,23 @@ def main():
         batched_form("cdf97 fwd f32 5 levels, batched: 1024 images 256x256", [(256, 256)] * 1024, seed=2, steps=10)
 
         # the same 1024 equal-size images as one plane batch (one launch per level)
-        xp = torch.rand((1024, 256, 256), device=dev, generator=torch.Generator(device=dev).manual_seed(2))
-        yp = torch.empty_like(xp)
-        _, pr = time_steps(torch, lambda i: d.fwd(xp, "cdf97", 5, out=yp), 10, 2)
-        ms = float(np.median(pr))
-        ab = 1024 * algorithmic_bytes(256, 256, 5, 4)
-        forms.append({"form": "cdf97 fwd f32 5 levels, plane batch: 1024 images 256x256",
-                      "Gpixel/s": round(1024 * 256 * 256 / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
-                      "GB/s": round(ab / (ms * 1e-3) / 1e9, 1),
-                      "hbm_frac": round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
-        del xp, yp
+        pb_name = "cdf97 fwd f32 5 levels, plane batch: 1024 images 256x256"
+        if want(pb_name):
+            xp = torch.rand((1024, 256, 256), device=dev, generator=torch.Generator(device=dev).manual_seed(2))
+            yp = torch.empty_like(xp)
+            _, pr = time_steps(torch, lambda i: d.fwd(xp, "cdf97", 5, out=yp), 10, 2)
+            ms = float(np.median(pr))
+            ab = 1024 * algorithmic_bytes(256, 256, 5, 4)
+            forms.append({"form": pb_name,
+                          "Gpixel/s": round(1024 * 256 * 256 / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
+                          "GB/s": round(ab / (ms * 1e-3) / 1e9, 1),
+                          "hbm_frac": round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+            del xp, yp
 
 
     cpu = None if args.no_cpu else cpu_baseline(x_host, args.cpu_seconds)
+    if cpu is not None:
+        cpu["pool"] = pool
 
     line = {
         "metric": "Gpixel/s 2-D CDF 9/7 fwd 8192^2 FP32 (+ % HBM roofline)",
