@@ -245,6 +245,10 @@ int run_forward(const void* src, void* dst, int32_t planes, int64_t sps, int64_t
                  aligned(lp.out, sv * es) && lp.out_pitch % sv == 0 && stride_ok(planes, lp.out_ps, sv) &&
                  nEc % sv == 0 && aligned(lp.out_ll, sv * es) && lp.out_ll_pitch % sv == 0 &&
                  stride_ok(planes, lp.out_ll_ps, sv);
+        // sample pairs: every row base (and plane stride) 8-byte aligned
+        lp.vec8 = aligned(lp.in, 2 * es) && lp.in_pitch % 2 == 0 && stride_ok(planes, lp.in_ps, 2) &&
+                  aligned(lp.out, 2 * es) && lp.out_pitch % 2 == 0 && stride_ok(planes, lp.out_ps, 2) &&
+                  aligned(lp.out_ll, 2 * es) && lp.out_ll_pitch % 2 == 0 && stride_ok(planes, lp.out_ll_ps, 2);
         const int rc = launch_planes(dwt2::kForward, wavelet, dtype, flags, lp, planes, es, s);
         if (rc) return rc;
         in = lp.out_ll;

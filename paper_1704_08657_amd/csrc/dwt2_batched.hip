@@ -134,9 +134,14 @@ batched_level_kernel(const dwt2_image* imgs, int count, int levels, int l, unsig
     P.vec = is_aligned(P.in, 4 * es) && P.in_pitch % 4 == 0 && is_aligned(P.out, BPL * es) &&
             P.out_pitch % BPL == 0 && ((wl + 1) / 2) % BPL == 0 && is_aligned(P.out_ll, BPL * es) &&
             P.out_ll_pitch % BPL == 0;
+    P.vec8 = is_aligned(P.in, 2 * es) && P.in_pitch % 2 == 0 && is_aligned(P.out, 2 * es) &&
+             P.out_pitch % 2 == 0 && is_aligned(P.out_ll, 2 * es) && P.out_ll_pitch % 2 == 0;
     const int ty = tt / P.tiles_x;
     const int tx = tt - ty * P.tiles_x;
-    tile_body<kForward, kCdf97, T, SPLIT ? kSchemeSplit : kSchemeFused, NW, K, BPL>(P, tx, ty, lds, lane, wv);
+    // images whose rows are only 8-byte aligned: semi-vector interior tiles
+    constexpr int SCH = SPLIT ? kSchemeSplit : kSchemeFused;
+    if (!P.vec && P.vec8) tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, true>(P, tx, ty, lds, lane, wv);
+    else tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, false>(P, tx, ty, lds, lane, wv);
 }
 
 template <typename T, bool SPLIT, int NW, int K, int BPL>

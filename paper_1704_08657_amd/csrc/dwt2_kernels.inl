@@ -994,6 +994,35 @@ __device__ __forceinline__ void storeN(T* rowp, int gc, int ncols, bool vec, con
     }
 }
 
+// Semi-vector access for rows that are only 8-byte aligned (even pitches):
+// four image samples as two pairs, a subband row segment as pairs when its
+// base is even, else sample by sample.  Interior tiles only (no bounds).
+template <typename T>
+__device__ __forceinline__ void load4_pairs(const T* base, int64_t pitch, int row, int c, typename St<T>::V& v0,
+                                            typename St<T>::V& v1, typename St<T>::V& v2,
+                                            typename St<T>::V& v3) {
+    const T* p = base + (int64_t)row * pitch + c;
+    const Pack2<T> q0 = *reinterpret_cast<const Pack2<T>*>(p);
+    const Pack2<T> q1 = *reinterpret_cast<const Pack2<T>*>(p + 2);
+    v0 = St<T>::load(q0.v[0]); v1 = St<T>::load(q0.v[1]);
+    v2 = St<T>::load(q1.v[0]); v3 = St<T>::load(q1.v[1]);
+}
+template <typename T>
+__device__ __forceinline__ void nt_store1(T* p, T a) {
+    if constexpr (sizeof(T) == 4) __builtin_nontemporal_store(__builtin_bit_cast(int, a), reinterpret_cast<int*>(p));
+    else __builtin_nontemporal_store(__builtin_bit_cast(short, a), reinterpret_cast<short*>(p));
+}
+template <typename T, int N>
+__device__ __forceinline__ void storeN_pairs(T* p, bool pairs, const typename St<T>::V (&v)[N]) {
+    if (pairs) {
+#pragma unroll
+        for (int i = 0; i < N; i += 2) nt_store2(p + i, St<T>::store(v[i]), St<T>::store(v[i + 1]));
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) nt_store1(p + i, St<T>::store(v[i]));
+    }
+}
+
 // Load the tile into registers: the core rows of the lane (a) and, in the
 // halo lanes, the lane's halo blocks (e).
 template <int DIR, typename T, bool EDGE, int BPL, int K>
@@ -1227,9 +1256,71 @@ __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::B
     }
 }
 
+// Forward interior tile of an image whose rows are only 8-byte aligned
+// (vec8): the loads of load_tile as sample pairs; the stores of store_tile
+// as pairs where the subband row base is even (LL, LH always; HL, HH when
+// the low-pass width is even), else sample by sample.
+template <typename T, int BPL, int K>
+__device__ __forceinline__ void load_tile_semi(typename St<T>::V (&a)[K][Lay<BPL>::BX], typename St<T>::V (&e)[8],
+                                               const LevelParams& P, const Geo& g, const TileGeo<BPL>& tg,
+                                               int lane) {
+    using V = typename St<T>::V;
+    const T* in = static_cast<const T*>(P.in);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) e[q] = V(0);
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const int row = 2 * (g.gr0 + r);
+#pragma unroll
+        for (int q = 0; q < BPL / 2; ++q) {
+            const int c = 2 * g.gcL + 4 * q;
+            V* b0 = &a[r][8 * q];
+            load4_pairs<T>(in, P.in_pitch, row, c, b0[0], b0[1], b0[4], b0[5]);
+            load4_pairs<T>(in, P.in_pitch, row + 1, c, b0[2], b0[3], b0[6], b0[7]);
+        }
+    }
+    if (lane < 32 && tg.re < K) {
+        const int row = 2 * tg.gre;
+        load4_pairs<T>(in, P.in_pitch, row, 2 * tg.ge[0], e[0], e[1], e[4], e[5]);
+        load4_pairs<T>(in, P.in_pitch, row + 1, 2 * tg.ge[0], e[2], e[3], e[6], e[7]);
+    }
+}
+
+template <typename T, int NW, int BPL, int K>
+__device__ __forceinline__ void store_tile_semi(typename St<T>::V (&a)[K][Lay<BPL>::BX], const LevelParams& P,
+                                                const Geo& g, int wv) {
+    using V = typename St<T>::V;
+    constexpr int kCoreBY = NW * K - 2 * kHalo;
+    T* ll = static_cast<T*>(P.out_ll);
+    T* det = static_cast<T*>(P.out);
+    const bool hi_pairs = (g.nEc & 1) == 0;       // HL, HH rows start at column nEc
+    constexpr bool kBySubband = sizeof(T) == 4;
+#pragma unroll
+    for (int k0 = 0; k0 < (kBySubband ? 4 : 1); ++k0)
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const int tr = wv * K + r;
+            if (tr < kHalo || tr >= kHalo + kCoreBY) continue;
+            const int gr = g.gr0 + r;
+#pragma unroll
+            for (int k = (kBySubband ? k0 : 0); k < (kBySubband ? k0 + 1 : 4); ++k) {
+                V v[BPL];
+#pragma unroll
+                for (int b = 0; b < BPL; ++b) v[b] = a[r][4 * b + k];
+                T* row = k == 0 ? ll + (int64_t)gr * P.out_ll_pitch
+                       : k == 1 ? det + (int64_t)gr * P.out_pitch + g.nEc
+                       : k == 2 ? det + (int64_t)(g.nEr + gr) * P.out_pitch
+                                : det + (int64_t)(g.nEr + gr) * P.out_pitch + g.nEc;
+                storeN_pairs<T, BPL>(row + g.gcL, (k & 1) ? hi_pairs : true, v);
+            }
+        }
+}
+
 // One tile (tx, ty) of one level: load, the fused steps, store.  The LDS
 // belongs to the calling work-group.
-template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL>
+// SEMI (forward): interior tiles of images with 8-byte aligned rows (vec8)
+// take the semi-vector path instead of the border path.
+template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL, bool SEMI = false>
 __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
                                           TileLds<typename St<T>::V, NW, BPL, K>& lds, int lane, int wv) {
     using V = typename St<T>::V;
@@ -1250,15 +1341,24 @@ __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
     tg.ge[1] = tg.ge[0] + 1;
     // Interior tile: every loaded block has all four components, no
     // neighbour index of the core's dependency cone needs clamping, and (the
-    // image's rows being aligned) every access is a full vector.
-    const bool interior = P.vec && rb0 - kHalo >= 0 && cb0 - kHalo >= 0 &&
-                          rb0 + kCoreBY + kHalo <= g.nOr && cb0 + L::CORE_BX + kHalo <= g.nOc;
+    // image's rows being aligned) every access is a full vector (SEMI: a
+    // pair of samples).
+    const bool inside = rb0 - kHalo >= 0 && cb0 - kHalo >= 0 &&
+                        rb0 + kCoreBY + kHalo <= g.nOr && cb0 + L::CORE_BX + kHalo <= g.nOc;
+    const bool interior = (SEMI ? P.vec8 != 0 : P.vec != 0) && inside;
     V a[K][L::BX];
     V e[8];
+    static_assert(!SEMI || DIR == kForward, "the semi-vector path is a forward path");
     if (interior) {
-        load_tile<DIR, T, false, BPL>(a, e, P, g, tg, lane);
-        run<DIR, WAV, false, SCH, NW, BPL>(a, e, lds, lane, wv, g, tg);
-        store_tile<DIR, T, false, NW, BPL>(a, P, g, wv);
+        if constexpr (SEMI) {
+            load_tile_semi<T, BPL>(a, e, P, g, tg, lane);
+            run<DIR, WAV, false, SCH, NW, BPL>(a, e, lds, lane, wv, g, tg);
+            store_tile_semi<T, NW, BPL>(a, P, g, wv);
+        } else {
+            load_tile<DIR, T, false, BPL>(a, e, P, g, tg, lane);
+            run<DIR, WAV, false, SCH, NW, BPL>(a, e, lds, lane, wv, g, tg);
+            store_tile<DIR, T, false, NW, BPL>(a, P, g, wv);
+        }
     } else if constexpr (DIR != kAdjoint) {
         // border tile: symmetric extension at load time, unclamped steps
         // (the split applies to interior tiles only)
@@ -1287,7 +1387,7 @@ __device__ __forceinline__ LevelParams plane_params(const LevelParams& P, int pl
     return Q;
 }
 
-template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL>
+template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL, bool SEMI>
 __global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
     using V = typename St<T>::V;
     __shared__ TileLds<V, NW, BPL, K> lds;
@@ -1310,7 +1410,7 @@ __global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
     const int t = g - pl * nt;
     const int ty = t / P.tiles_x;
     const int tx = t - ty * P.tiles_x;
-    tile_body<DIR, WAV, T, SCH, NW, K, BPL>(plane_params<T>(P, pl), tx, ty, lds, lane, wv);
+    tile_body<DIR, WAV, T, SCH, NW, K, BPL, SEMI>(plane_params<T>(P, pl), tx, ty, lds, lane, wv);
 }
 
 // ===========================================================================

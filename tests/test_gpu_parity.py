@@ -337,3 +337,42 @@ def test_plane_batch_equals_single_planes(shape, lv):
             assert torch.equal(a[k], d.adj(y[k], lv, config=cfg)), (cfg, k)
             assert torch.equal(yi[k], d.fwd(xi[k], "cdf53", lv, config=cfg)), (cfg, k)
     assert rel_err(host(y[0]), lifting.fwd(host(x[0]), "cdf97", lv)) <= TOL97
+
+
+# ---- the semi-vector interior path (rows only 8-byte aligned) ---------------
+def fwd_pitched(x, wavelet, lv, dst_pitch, config):
+    """Forward through the raw C ABI into a destination of row pitch
+    `dst_pitch` (elements); returns the h x w pyramid."""
+    h, w = x.shape
+    dt = d.dtype_code(x)
+    dst = torch.zeros((h, dst_pitch), dtype=x.dtype, device=dev())
+    ws = d.workspace(h, w, lv, dt, dev())
+    wsp = ctypes.c_void_p(ws.data_ptr() if ws is not None else 0)
+    st = d.dwt2_fwd(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(dst.data_ptr()), h, w, w, dst_pitch,
+                    dt, d.WAVELETS[wavelet], lv, 0, d.DWT2_FLAG_KERNEL(config), wsp,
+                    ws.numel() if ws is not None else 0, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0, st
+    return dst[:, :w]
+
+
+@pytest.mark.parametrize("shape", [(1034, 2062), (600, 1030), (520, 2054), (1100, 2052)])
+def test_semi_vector_path_bit_identical(shape):
+    """Widths of 2 mod 4 (odd low-pass width) and subband widths of 2 mod 4
+    (for 4-block tiles): with an even destination pitch the interior tiles
+    take the semi-vector path, with an odd one the border path everywhere.
+    Both compute the same arithmetic, so they agree bit for bit; the result
+    is also checked against the oracle."""
+    h, w = shape
+    xf = gpu(workloads.uniform(h, w, seed=61))
+    xi = gpu(workloads.pixels_u8(h, w, seed=62))
+    ref = lifting.fwd(host(xf), "cdf97", 3)
+    for cfg in tile_configs():
+        for x, wav in ((xf, "cdf97"), (xf.to(torch.bfloat16), "cdf97"), (xf, "cdf53f"), (xi, "cdf53")):
+            for lv in (1, 3):
+                say("semi-vector path", shape, cfg, wav, x.dtype, lv)
+                even = fwd_pitched(x, wav, lv, w + 2 if w % 4 == 0 else w, cfg)
+                odd = fwd_pitched(x, wav, lv, w + 1, cfg)
+                assert torch.equal(even, odd), (cfg, wav, x.dtype, lv)
+                assert torch.equal(even, d.fwd(x, wav, lv, config=cfg)), (cfg, wav, x.dtype, lv)
+        y = fwd_pitched(xf, "cdf97", 3, w, cfg)
+        assert rel_err(host(y), ref) <= TOL97, cfg
