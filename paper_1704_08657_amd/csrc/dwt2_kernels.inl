@@ -1013,14 +1013,9 @@ __device__ __forceinline__ void nt_store1(T* p, T a) {
     else __builtin_nontemporal_store(__builtin_bit_cast(short, a), reinterpret_cast<short*>(p));
 }
 template <typename T, int N>
-__device__ __forceinline__ void storeN_pairs(T* p, bool pairs, const typename St<T>::V (&v)[N]) {
-    if (pairs) {
+__device__ __forceinline__ void storeN_pairs(T* p, const typename St<T>::V (&v)[N]) {
 #pragma unroll
-        for (int i = 0; i < N; i += 2) nt_store2(p + i, St<T>::store(v[i]), St<T>::store(v[i + 1]));
-    } else {
-#pragma unroll
-        for (int i = 0; i < N; ++i) nt_store1(p + i, St<T>::store(v[i]));
-    }
+    for (int i = 0; i < N; i += 2) nt_store2(p + i, St<T>::store(v[i]), St<T>::store(v[i + 1]));
 }
 
 // Load the tile into registers: the core rows of the lane (a) and, in the
@@ -1256,10 +1251,24 @@ __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::B
     }
 }
 
+// A subband row segment whose first sample sits at an odd element offset
+// (HL, HH rows when the low-pass width is odd): the pairs start one sample
+// later, each lane pairing its last sample with the next lane's first (DPP);
+// lane 0 stores the tile's first sample alone, lane 63 its last.
+template <typename T, int N>
+__device__ __forceinline__ void storeN_shifted(T* p, const typename St<T>::V (&v)[N], int lane) {
+    using V = typename St<T>::V;
+    const V next = from_right(v[0]);
+#pragma unroll
+    for (int i = 1; i + 1 < N; i += 2) nt_store2(p + i, St<T>::store(v[i]), St<T>::store(v[i + 1]));
+    if (lane < kLanes - 1) nt_store2(p + N - 1, St<T>::store(v[N - 1]), St<T>::store(next));
+    else nt_store1(p + N - 1, St<T>::store(v[N - 1]));
+    if (lane == 0) nt_store1(p, St<T>::store(v[0]));
+}
+
 // Forward interior tile of an image whose rows are only 8-byte aligned
 // (vec8): the loads of load_tile as sample pairs; the stores of store_tile
-// as pairs where the subband row base is even (LL, LH always; HL, HH when
-// the low-pass width is even), else sample by sample.
+// as pairs (HL, HH rows starting at an odd offset: shifted pairs).
 template <typename T, int BPL, int K>
 __device__ __forceinline__ void load_tile_semi(typename St<T>::V (&a)[K][Lay<BPL>::BX], typename St<T>::V (&e)[8],
                                                const LevelParams& P, const Geo& g, const TileGeo<BPL>& tg,
@@ -1288,7 +1297,7 @@ __device__ __forceinline__ void load_tile_semi(typename St<T>::V (&a)[K][Lay<BPL
 
 template <typename T, int NW, int BPL, int K>
 __device__ __forceinline__ void store_tile_semi(typename St<T>::V (&a)[K][Lay<BPL>::BX], const LevelParams& P,
-                                                const Geo& g, int wv) {
+                                                const Geo& g, int wv, int lane) {
     using V = typename St<T>::V;
     constexpr int kCoreBY = NW * K - 2 * kHalo;
     T* ll = static_cast<T*>(P.out_ll);
@@ -1311,7 +1320,8 @@ __device__ __forceinline__ void store_tile_semi(typename St<T>::V (&a)[K][Lay<BP
                        : k == 1 ? det + (int64_t)gr * P.out_pitch + g.nEc
                        : k == 2 ? det + (int64_t)(g.nEr + gr) * P.out_pitch
                                 : det + (int64_t)(g.nEr + gr) * P.out_pitch + g.nEc;
-                storeN_pairs<T, BPL>(row + g.gcL, (k & 1) ? hi_pairs : true, v);
+                if ((k & 1) && !hi_pairs) storeN_shifted<T, BPL>(row + g.gcL, v, lane);
+                else storeN_pairs<T, BPL>(row + g.gcL, v);
             }
         }
 }
@@ -1353,7 +1363,7 @@ __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
         if constexpr (SEMI) {
             load_tile_semi<T, BPL>(a, e, P, g, tg, lane);
             run<DIR, WAV, false, SCH, NW, BPL>(a, e, lds, lane, wv, g, tg);
-            store_tile_semi<T, NW, BPL>(a, P, g, wv);
+            store_tile_semi<T, NW, BPL>(a, P, g, wv, lane);
         } else {
             load_tile<DIR, T, false, BPL>(a, e, P, g, tg, lane);
             run<DIR, WAV, false, SCH, NW, BPL>(a, e, lds, lane, wv, g, tg);
