@@ -376,3 +376,37 @@ def test_semi_vector_path_bit_identical(shape):
                 assert torch.equal(even, d.fwd(x, wav, lv, config=cfg)), (cfg, wav, x.dtype, lv)
         y = fwd_pitched(xf, "cdf97", 3, w, cfg)
         assert rel_err(host(y), ref) <= TOL97, cfg
+
+
+def test_multilevel_graph_replay():
+    """A 5-level forward + inverse of a plane stack (one launch per level,
+    workspace from the graph's pool) captured in a graph and replayed with
+    eager work and synchronisations in between; every replay must equal
+    the eager result."""
+    x = gpu(workloads.planes(2, 700, 1030, seed=71))
+    y = torch.empty_like(x)
+    r = torch.empty_like(x)
+
+    def step():
+        d.fwd(x, "cdf97", 5, out=y)
+        d.inv(y, "cdf97", 5, out=r)
+    step()
+    torch.cuda.synchronize()
+    ey, er = y.clone(), r.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        step()
+    for rep in range(3):
+        y.fill_(float("nan"))
+        r.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, ey) and torch.equal(r, er), rep
+    assert rel_err(host(y[1]), lifting.fwd(host(x[1]), "cdf97", 5)) <= TOL97
