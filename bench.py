@@ -5,7 +5,11 @@ Headline workload: CDF 9/7 forward transform, one level, of one 8192 x 8192
 FP32 image (pixels uniform in [0, 1), seed 0), whole-point symmetric borders.
 A step is one dwt2_fwd call on that image; inputs are resident in HBM before
 the timed region, and three input/output pairs are rotated so that the 256 MB
-Infinity Cache cannot serve a step from the previous step's data.
+Infinity Cache cannot serve a step from the previous step's data.  The steps
+run back to back; one HIP event pair around the timed region gives the
+kernel's average launch time (an event pair per step would add several
+microseconds to every step), and a separate sample of 100 individually
+bracketed launches gives their spread.
 
 Printed: one JSON line with the contract fields, a `roofline` object for the
 level kernel (algorithmic bytes: each pixel read once, each coefficient
@@ -13,8 +17,8 @@ written once = 2 * 4 B/px) and a `cpu_baseline` object (the CPU oracle timed
 on a bounded crop of the same image).  `forms` lists the other forms of the
 path, measured the same way with fewer steps: 5 levels, the P0/P1 split,
 inverse, the separable comparison scheme (twice the steps and barriers),
-the factored fused steps, real CDF 5/3, BF16 / FP16 storage, reversible 5/3, warm and gradient-input
-variants, 1024^2 (per call and under graph replay), 4096^2 (cold and warm)
+the factored fused steps, real CDF 5/3, BF16 / FP16 storage, reversible
+5/3, warm and gradient-input variants, 1024^2 (per call and under graph replay), 4096^2 (cold and warm)
 and 16384^2 images, 3 x 8192^2 planes forward + inverse at each storage type
 with coefficient error and reconstruction PSNR, the autograd training step
 (64 x 3 x 1024^2, forward + adjoint backward), and the batched forward
@@ -95,23 +99,39 @@ def algorithmic_bytes(h, w, levels, elem):
 
 
 def time_steps(torch, fn, steps, warmup):
-    """Run warmup untimed steps, then time `steps` steps.  Returns (total ms
-    between synchronisations, per-step event durations in ms)."""
+    """Run warmup untimed steps, then time `steps` back-to-back steps.
+    Returns (total ms between the synchronisations, the steps' average ms
+    from one HIP event pair around the whole timed region on the stream the
+    kernels run on).  No event sits between the steps: an event pair per
+    step costs several microseconds per step on this GPU."""
     stream = torch.cuda.current_stream()
     for i in range(warmup):
         fn(i)
     torch.cuda.synchronize()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    start.record(stream)
     for i in range(steps):
+        fn(i)
+    end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = (time.perf_counter() - t0) * 1e3
+    return total_ms, start.elapsed_time(end) / steps
+
+
+def per_launch_sample(torch, fn, n):
+    """Durations (ms) of n launches, each bracketed by its own event pair
+    (the pair itself adds a few microseconds to what it brackets)."""
+    stream = torch.cuda.current_stream()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+    for i in range(n):
         starts[i].record(stream)
         fn(i)
         ends[i].record(stream)
     torch.cuda.synchronize()
-    total_ms = (time.perf_counter() - t0) * 1e3
-    per = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    return total_ms, per
+    return [a.elapsed_time(b) for a, b in zip(starts, ends)]
 
 
 def cpu_baseline(x, seconds):
@@ -217,26 +237,27 @@ def main():
     head_cfg = d.tuned_config("fwd", "cdf97", d.DWT2_F32, N, N, 1)
     if head_cfg is None:
         head_cfg = "default"
-    total_ms, per = time_steps(torch, fwd_step, args.steps, args.warmup)
+    total_ms, kern_ms = time_steps(torch, fwd_step, args.steps, args.warmup)
     ms_step = total_ms / args.steps
     px = N * N
     value = px / (ms_step * 1e-3) / 1e9
-    kern_ms = float(np.mean(per))
+    per = per_launch_sample(torch, fwd_step, 100)
     abytes = algorithmic_bytes(N, N, 1, 4)
     achieved = abytes / (kern_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "kernel": f"level_kernel<fwd, cdf97, f32>, kernel configuration {head_cfg}",
                 "algorithmic_bytes_per_launch": abytes,
-                "avg_launch_ms": round(kern_ms, 5), "median_launch_ms": round(float(np.median(per)), 5),
-                "p10_launch_ms": round(float(np.percentile(per, 10)), 5),
-                "p90_launch_ms": round(float(np.percentile(per, 90)), 5)}
+                "avg_launch_ms": round(kern_ms, 5),
+                "per_launch_sample": {"launches": len(per), "median_ms": round(float(np.median(per)), 5),
+                                      "p10_ms": round(float(np.percentile(per, 10)), 5),
+                                      "p90_ms": round(float(np.percentile(per, 90)), 5),
+                                      "note": "after the timed region, an event pair around each launch"}}
 
     # a plain device copy of one input to one output buffer (N*N*4 bytes read
     # and written) on the same rotating buffers: the box's streaming bandwidth
-    _, per_c = time_steps(torch, lambda i: ys[i % pairs].copy_(xs[i % pairs]), 20, 3)
-    cms = float(np.median(per_c))
-    copy_ref = {"bytes_per_launch": 2 * N * N * 4, "median_ms": round(cms, 5),
+    _, cms = time_steps(torch, lambda i: ys[i % pairs].copy_(xs[i % pairs]), 50, 5)
+    copy_ref = {"bytes_per_launch": 2 * N * N * 4, "avg_ms": round(cms, 5),
                 "GB/s": round(2 * N * N * 4 / (cms * 1e-3) / 1e9, 1), "kernel": "torch copy_"}
     roofline["of_copy"] = round(achieved / copy_ref["GB/s"], 4)
 
@@ -251,8 +272,7 @@ def main():
                 return
             if tune_key is not None:
                 tune(name, *tune_key, levels, lambda c, i: fn(i, c))
-            tot, pr = time_steps(torch, lambda i: fn(i, None), steps, 5)
-            ms = float(np.median(pr))
+            _, ms = time_steps(torch, lambda i: fn(i, None), steps, 5)
             ab = algorithmic_bytes(N, N, levels, elem)
             forms.append({"form": name, "Gpixel/s": round(px / (ms * 1e-3) / 1e9, 2),
                           "ms": round(ms, 4), "GB/s": round(ab / (ms * 1e-3) / 1e9, 1),
@@ -331,8 +351,7 @@ def main():
             yn = [torch.empty_like(t) for t in xn]
             def run(i):
                 d.fwd(xn[i % npairs], "cdf97", levels, out=yn[i % npairs])
-            _, pr = time_steps(torch, run, steps, 5)
-            ms = float(np.median(pr))
+            _, ms = time_steps(torch, run, steps, 5)
             ab = algorithmic_bytes(n, n, levels, 4)
             entry = {"form": name, "Gpixel/s": round(n * n / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 5),
                      "GB/s": round(ab / (ms * 1e-3) / 1e9, 1),
@@ -350,8 +369,8 @@ def main():
                 with torch.cuda.graph(gr, stream=s2):
                     for i in range(graph_calls):
                         run(i)
-                _, pg = time_steps(torch, lambda i: gr.replay(), 20, 3)
-                gms = float(np.median(pg)) / graph_calls
+                _, gms = time_steps(torch, lambda i: gr.replay(), 20, 3)
+                gms /= graph_calls
                 entry.update({"graph_calls": graph_calls, "graph_ms_per_call": round(gms, 5),
                               "graph_Gpixel/s": round(n * n / (gms * 1e-3) / 1e9, 2)})
                 del gr
@@ -387,8 +406,7 @@ def main():
             def fwd_inv(i, xq=xq, cq=cq, rq=rq):
                 d.fwd(xq, "cdf97", 5, out=cq)
                 d.inv(cq, "cdf97", 5, out=rq)
-            _, pr = time_steps(torch, fwd_inv, 10, 2)
-            ms = float(np.median(pr))
+            _, ms = time_steps(torch, fwd_inv, 10, 2)
             el = 4 if tdt == torch.float32 else 2
             ab = 2 * 3 * algorithmic_bytes(N, N, 5, el)
             entry = {"form": f"cdf97 fwd+inv {nm} 5 levels, 3 x {N}^2 planes",
@@ -429,8 +447,7 @@ def main():
             loss.backward()
             xa.grad = None
         if want(ag_name):
-            _, pr = time_steps(torch, train_step, 10, 2)
-            ms = float(np.median(pr))
+            _, ms = time_steps(torch, train_step, 10, 2)
             ab = 2 * 64 * 3 * algorithmic_bytes(1024, 1024, 3, 4)
             forms.append({"form": ag_name,
                           "Gpixel/s": round(64 * 3 * 1024 * 1024 / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
@@ -445,8 +462,7 @@ def main():
             g = torch.Generator(device=dev).manual_seed(seed)
             imgs = [torch.rand(s, device=dev, generator=g) for s in shapes]
             call = d.BatchedForward(imgs, 5)
-            _, pr = time_steps(torch, lambda i: call.run(), steps, 2)
-            ms = float(np.median(pr))
+            _, ms = time_steps(torch, lambda i: call.run(), steps, 2)
             # the same call captured once in a graph and replayed
             s2 = torch.cuda.Stream()
             s2.wait_stream(torch.cuda.current_stream())
@@ -457,8 +473,7 @@ def main():
             gr = torch.cuda.CUDAGraph()
             with torch.cuda.graph(gr, stream=s2):
                 call.run()
-            _, pg = time_steps(torch, lambda i: gr.replay(), steps, 2)
-            gms = float(np.median(pg))
+            _, gms = time_steps(torch, lambda i: gr.replay(), steps, 2)
             npx = sum(h * w for h, w in shapes)
             ab = sum(algorithmic_bytes(h, w, 5, 4) for h, w in shapes)
             forms.append({"form": name, "Gpixel/s": round(npx / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
@@ -478,8 +493,7 @@ def main():
         if want(pb_name):
             xp = torch.rand((1024, 256, 256), device=dev, generator=torch.Generator(device=dev).manual_seed(2))
             yp = torch.empty_like(xp)
-            _, pr = time_steps(torch, lambda i: d.fwd(xp, "cdf97", 5, out=yp), 10, 2)
-            ms = float(np.median(pr))
+            _, ms = time_steps(torch, lambda i: d.fwd(xp, "cdf97", 5, out=yp), 10, 2)
             ab = 1024 * algorithmic_bytes(256, 256, 5, 4)
             forms.append({"form": pb_name,
                           "Gpixel/s": round(1024 * 256 * 256 / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),

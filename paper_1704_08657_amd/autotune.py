@@ -85,18 +85,20 @@ def tune_case(direction: str, wavelet: str, dtype: str, h: int, w: int, levels: 
 
 
 def _time(torch, fn, steps=20, warm=4):
+    """Average ms per call of `steps` back-to-back calls, from one event pair
+    around them (an event pair per call would add its own cost to each)."""
     stream = torch.cuda.current_stream()
     for i in range(warm):
         fn(i)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
     for i in range(steps):
-        ev[i][0].record(stream)
         fn(i)
-        ev[i][1].record(stream)
+    b.record(stream)
     torch.cuda.synchronize()
-    ts = sorted(a.elapsed_time(b) for a, b in ev)
-    return ts[len(ts) // 2]
+    return a.elapsed_time(b) / steps
 
 
 def tune(sizes=(256, 1024, 4096, 8192), levels=(1, 5), quick=False, out=CACHE_PATH, log=print):
