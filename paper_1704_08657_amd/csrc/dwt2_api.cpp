@@ -293,6 +293,10 @@ int run_backward(dwt2::Direction dir, const void* src, void* dst, int32_t planes
                  nEc % sv == 0 && aligned(lp.in_ll, sv * es) && lp.in_ll_pitch % sv == 0 &&
                  stride_ok(planes, lp.in_ll_ps, sv) && aligned(lp.out, 4 * es) && lp.out_pitch % 4 == 0 &&
                  stride_ok(planes, lp.out_ps, 4);
+        // sample pairs: every row base (and plane stride) 8-byte aligned
+        lp.vec8 = aligned(lp.in, 2 * es) && lp.in_pitch % 2 == 0 && stride_ok(planes, lp.in_ps, 2) &&
+                  aligned(lp.in_ll, 2 * es) && lp.in_ll_pitch % 2 == 0 && stride_ok(planes, lp.in_ll_ps, 2) &&
+                  aligned(lp.out, 2 * es) && lp.out_pitch % 2 == 0 && stride_ok(planes, lp.out_ps, 2);
         const int rc = launch_planes(dir, wavelet, dtype, flags, lp, planes, es, s);
         if (rc) return rc;
         ll = lp.out;

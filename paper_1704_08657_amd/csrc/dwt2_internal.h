@@ -85,9 +85,9 @@ struct LevelParams {
     // the streaming kernel takes one grid row per plane).
     int64_t in_ps, in_ll_ps, out_ps, out_ll_ps;
     int32_t planes;
-    // Forward without `vec`: every row base (and plane stride) is 8-byte
-    // aligned (even pitches), so interior tiles can use pairs of samples
-    // (the semi-vector interior path).
+    // Without `vec`: every row base (and plane stride) is 8-byte aligned
+    // (even pitches), so interior tiles can use pairs of samples (the
+    // semi-vector interior path).
     int32_t vec8;
 };
 

@@ -1266,70 +1266,154 @@ __device__ __forceinline__ void storeN_shifted(T* p, const typename St<T>::V (&v
     if (lane == 0) nt_store1(p, St<T>::store(v[0]));
 }
 
-// Forward interior tile of an image whose rows are only 8-byte aligned
-// (vec8): the loads of load_tile as sample pairs; the stores of store_tile
-// as pairs (HL, HH rows starting at an odd offset: shifted pairs).
-template <typename T, int BPL, int K>
+// The load counterpart of storeN_shifted: a subband row segment whose first
+// sample sits at an odd element offset is read as pairs starting one sample
+// later; each lane's first sample is the previous lane's last pair's second
+// (DPP), lane 0 reads its first sample alone.  The last lane's last pair
+// reaches one sample into the next tile (inside the image for interior
+// tiles).
+template <typename T, int N>
+__device__ __forceinline__ void loadN_shifted(const T* p, typename St<T>::V (&v)[N], int lane) {
+    using V = typename St<T>::V;
+    V last;
+#pragma unroll
+    for (int i = 1; i < N; i += 2) {
+        const Pack2<T> q = *reinterpret_cast<const Pack2<T>*>(p + i);
+        v[i] = St<T>::load(q.v[0]);
+        if (i + 1 < N) v[i + 1] = St<T>::load(q.v[1]);
+        else last = St<T>::load(q.v[1]);
+    }
+    const V first = from_left(last);
+    if (lane == 0) v[0] = St<T>::load(p[0]);
+    else v[0] = first;
+}
+template <typename T, int N>
+__device__ __forceinline__ void loadN_pairs(const T* p, typename St<T>::V (&v)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; i += 2) {
+        const Pack2<T> q = *reinterpret_cast<const Pack2<T>*>(p + i);
+        v[i] = St<T>::load(q.v[0]);
+        v[i + 1] = St<T>::load(q.v[1]);
+    }
+}
+
+// Interior tile of an image whose rows are only 8-byte aligned (vec8): the
+// accesses of load_tile / store_tile as sample pairs; HL, HH rows starting at
+// an odd offset (odd low-pass width) as shifted pairs.
+template <int DIR, typename T, int BPL, int K>
 __device__ __forceinline__ void load_tile_semi(typename St<T>::V (&a)[K][Lay<BPL>::BX], typename St<T>::V (&e)[8],
                                                const LevelParams& P, const Geo& g, const TileGeo<BPL>& tg,
                                                int lane) {
     using V = typename St<T>::V;
-    const T* in = static_cast<const T*>(P.in);
 #pragma unroll
     for (int q = 0; q < 8; ++q) e[q] = V(0);
+    const bool halo_lane = lane < 32 && tg.re < K;
+    if constexpr (DIR == kForward) {
+        const T* in = static_cast<const T*>(P.in);
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
-        const int row = 2 * (g.gr0 + r);
+        for (int r = 0; r < K; ++r) {
+            const int row = 2 * (g.gr0 + r);
 #pragma unroll
-        for (int q = 0; q < BPL / 2; ++q) {
-            const int c = 2 * g.gcL + 4 * q;
-            V* b0 = &a[r][8 * q];
-            load4_pairs<T>(in, P.in_pitch, row, c, b0[0], b0[1], b0[4], b0[5]);
-            load4_pairs<T>(in, P.in_pitch, row + 1, c, b0[2], b0[3], b0[6], b0[7]);
+            for (int q = 0; q < BPL / 2; ++q) {
+                const int c = 2 * g.gcL + 4 * q;
+                V* b0 = &a[r][8 * q];
+                load4_pairs<T>(in, P.in_pitch, row, c, b0[0], b0[1], b0[4], b0[5]);
+                load4_pairs<T>(in, P.in_pitch, row + 1, c, b0[2], b0[3], b0[6], b0[7]);
+            }
         }
-    }
-    if (lane < 32 && tg.re < K) {
-        const int row = 2 * tg.gre;
-        load4_pairs<T>(in, P.in_pitch, row, 2 * tg.ge[0], e[0], e[1], e[4], e[5]);
-        load4_pairs<T>(in, P.in_pitch, row + 1, 2 * tg.ge[0], e[2], e[3], e[6], e[7]);
+        if (halo_lane) {
+            const int row = 2 * tg.gre;
+            load4_pairs<T>(in, P.in_pitch, row, 2 * tg.ge[0], e[0], e[1], e[4], e[5]);
+            load4_pairs<T>(in, P.in_pitch, row + 1, 2 * tg.ge[0], e[2], e[3], e[6], e[7]);
+        }
+    } else {
+        const T* ll = static_cast<const T*>(P.in_ll);
+        const T* det = static_cast<const T*>(P.in);
+        const bool hi_pairs = (g.nEc & 1) == 0;   // HL, HH rows start at column nEc
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const int64_t gr = g.gr0 + r;
+            const T* rows[4] = {ll + gr * P.in_ll_pitch, det + gr * P.in_pitch + g.nEc,
+                                det + (g.nEr + gr) * P.in_pitch, det + (g.nEr + gr) * P.in_pitch + g.nEc};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                V v[BPL];
+                if ((k & 1) && !hi_pairs) loadN_shifted<T, BPL>(rows[k] + g.gcL, v, lane);
+                else loadN_pairs<T, BPL>(rows[k] + g.gcL, v);
+#pragma unroll
+                for (int b = 0; b < BPL; ++b) a[r][4 * b + k] = v[b];
+            }
+        }
+        if (halo_lane) {
+            const int64_t gr = tg.gre;
+            const T* rows[4] = {ll + gr * P.in_ll_pitch, det + gr * P.in_pitch + g.nEc,
+                                det + (g.nEr + gr) * P.in_pitch, det + (g.nEr + gr) * P.in_pitch + g.nEc};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const T* p = rows[k] + tg.ge[0];
+                e[k] = St<T>::load(p[0]);
+                e[4 + k] = St<T>::load(p[1]);
+            }
+        }
     }
 }
 
-template <typename T, int NW, int BPL, int K>
+template <int DIR, typename T, int NW, int BPL, int K>
 __device__ __forceinline__ void store_tile_semi(typename St<T>::V (&a)[K][Lay<BPL>::BX], const LevelParams& P,
                                                 const Geo& g, int wv, int lane) {
     using V = typename St<T>::V;
     constexpr int kCoreBY = NW * K - 2 * kHalo;
-    T* ll = static_cast<T*>(P.out_ll);
-    T* det = static_cast<T*>(P.out);
-    const bool hi_pairs = (g.nEc & 1) == 0;       // HL, HH rows start at column nEc
-    constexpr bool kBySubband = sizeof(T) == 4;
+    if constexpr (DIR == kForward) {
+        T* ll = static_cast<T*>(P.out_ll);
+        T* det = static_cast<T*>(P.out);
+        const bool hi_pairs = (g.nEc & 1) == 0;   // HL, HH rows start at column nEc
+        constexpr bool kBySubband = sizeof(T) == 4;
 #pragma unroll
-    for (int k0 = 0; k0 < (kBySubband ? 4 : 1); ++k0)
+        for (int k0 = 0; k0 < (kBySubband ? 4 : 1); ++k0)
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                const int tr = wv * K + r;
+                if (tr < kHalo || tr >= kHalo + kCoreBY) continue;
+                const int gr = g.gr0 + r;
+#pragma unroll
+                for (int k = (kBySubband ? k0 : 0); k < (kBySubband ? k0 + 1 : 4); ++k) {
+                    V v[BPL];
+#pragma unroll
+                    for (int b = 0; b < BPL; ++b) v[b] = a[r][4 * b + k];
+                    T* row = k == 0 ? ll + (int64_t)gr * P.out_ll_pitch
+                           : k == 1 ? det + (int64_t)gr * P.out_pitch + g.nEc
+                           : k == 2 ? det + (int64_t)(g.nEr + gr) * P.out_pitch
+                                    : det + (int64_t)(g.nEr + gr) * P.out_pitch + g.nEc;
+                    if ((k & 1) && !hi_pairs) storeN_shifted<T, BPL>(row + g.gcL, v, lane);
+                    else storeN_pairs<T, BPL>(row + g.gcL, v);
+                }
+            }
+    } else {
+        T* img = static_cast<T*>(P.out);
 #pragma unroll
         for (int r = 0; r < K; ++r) {
             const int tr = wv * K + r;
             if (tr < kHalo || tr >= kHalo + kCoreBY) continue;
-            const int gr = g.gr0 + r;
+            const int64_t gr = g.gr0 + r;
 #pragma unroll
-            for (int k = (kBySubband ? k0 : 0); k < (kBySubband ? k0 + 1 : 4); ++k) {
-                V v[BPL];
-#pragma unroll
-                for (int b = 0; b < BPL; ++b) v[b] = a[r][4 * b + k];
-                T* row = k == 0 ? ll + (int64_t)gr * P.out_ll_pitch
-                       : k == 1 ? det + (int64_t)gr * P.out_pitch + g.nEc
-                       : k == 2 ? det + (int64_t)(g.nEr + gr) * P.out_pitch
-                                : det + (int64_t)(g.nEr + gr) * P.out_pitch + g.nEc;
-                if ((k & 1) && !hi_pairs) storeN_shifted<T, BPL>(row + g.gcL, v, lane);
-                else storeN_pairs<T, BPL>(row + g.gcL, v);
+            for (int q = 0; q < BPL / 2; ++q) {
+                const int c = 2 * g.gcL + 4 * q;
+                const V* b0 = &a[r][8 * q];
+                T* p0 = img + (2 * gr) * P.out_pitch + c;
+                T* p1 = p0 + P.out_pitch;
+                nt_store2(p0, St<T>::store(b0[0]), St<T>::store(b0[1]));
+                nt_store2(p0 + 2, St<T>::store(b0[4]), St<T>::store(b0[5]));
+                nt_store2(p1, St<T>::store(b0[2]), St<T>::store(b0[3]));
+                nt_store2(p1 + 2, St<T>::store(b0[6]), St<T>::store(b0[7]));
             }
         }
+    }
 }
 
 // One tile (tx, ty) of one level: load, the fused steps, store.  The LDS
 // belongs to the calling work-group.
-// SEMI (forward): interior tiles of images with 8-byte aligned rows (vec8)
-// take the semi-vector path instead of the border path.
+// SEMI: interior tiles of images with 8-byte aligned rows (vec8) take the
+// semi-vector path instead of the border path.
 template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL, bool SEMI = false>
 __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
                                           TileLds<typename St<T>::V, NW, BPL, K>& lds, int lane, int wv) {
@@ -1358,12 +1442,11 @@ __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
     const bool interior = (SEMI ? P.vec8 != 0 : P.vec != 0) && inside;
     V a[K][L::BX];
     V e[8];
-    static_assert(!SEMI || DIR == kForward, "the semi-vector path is a forward path");
     if (interior) {
         if constexpr (SEMI) {
-            load_tile_semi<T, BPL>(a, e, P, g, tg, lane);
+            load_tile_semi<DIR, T, BPL>(a, e, P, g, tg, lane);
             run<DIR, WAV, false, SCH, NW, BPL>(a, e, lds, lane, wv, g, tg);
-            store_tile_semi<T, NW, BPL>(a, P, g, wv, lane);
+            store_tile_semi<DIR, T, NW, BPL>(a, P, g, wv, lane);
         } else {
             load_tile<DIR, T, false, BPL>(a, e, P, g, tg, lane);
             run<DIR, WAV, false, SCH, NW, BPL>(a, e, lds, lane, wv, g, tg);

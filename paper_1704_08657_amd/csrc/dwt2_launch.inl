@@ -33,11 +33,11 @@ hipError_t launch_grid(const LevelParams& p, int planes, hipStream_t s) {
     return hipSuccess;
 }
 
-// The forward of an image whose rows are 8-byte but not vector aligned runs
-// its interior tiles on the semi-vector path (fused and split schemes).
+// An image whose rows are 8-byte but not vector aligned runs its interior
+// tiles on the semi-vector path (fused and split schemes).
 template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL>
 hipError_t launch_shape(const LevelParams& p, int planes, hipStream_t s) {
-    if constexpr (DIR == kForward && (SCH == kSchemeFused || SCH == kSchemeSplit)) {
+    if constexpr (SCH == kSchemeFused || SCH == kSchemeSplit) {
         if (!p.vec && p.vec8) return launch_grid<DIR, WAV, T, SCH, NW, K, BPL, true>(p, planes, s);
     }
     return launch_grid<DIR, WAV, T, SCH, NW, K, BPL, false>(p, planes, s);

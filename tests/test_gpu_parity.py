@@ -378,6 +378,50 @@ def test_semi_vector_path_bit_identical(shape):
         assert rel_err(host(y), ref) <= TOL97, cfg
 
 
+def back_pitched(fn, c, wavelet, lv, src_pitch, config):
+    """Inverse or adjoint through the raw C ABI from a source of row pitch
+    `src_pitch` (elements) holding the pyramid c; returns the h x w image."""
+    h, w = c.shape
+    dt = d.dtype_code(c)
+    src = torch.zeros((h, src_pitch), dtype=c.dtype, device=dev())
+    src[:, :w] = c
+    dst = torch.empty_like(c)
+    ws = d.workspace(h, w, lv, dt, dev())
+    wsp = ctypes.c_void_p(ws.data_ptr() if ws is not None else 0)
+    st = fn(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), h, w, src_pitch, w,
+            dt, d.WAVELETS[wavelet], lv, 0, d.DWT2_FLAG_KERNEL(config), wsp,
+            ws.numel() if ws is not None else 0, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0, st
+    return dst
+
+
+@pytest.mark.parametrize("shape", [(1034, 2062), (600, 1030), (1100, 2052)])
+def test_semi_vector_path_inverse_adjoint_bit_identical(shape):
+    """The inverse and adjoint of the same shapes: an even source pitch takes
+    the semi-vector path in the interior tiles, an odd one the border path
+    everywhere (destination contiguous, even width); bit for bit equal, and
+    the inverse restores the oracle's coefficients' image."""
+    h, w = shape
+    x = workloads.uniform(h, w, seed=63)
+    c = lifting.fwd(x, "cdf97", 3).astype(np.float32)
+    cg = gpu(c)
+    ci = gpu(lifting.fwd(workloads.pixels_u8(h, w, seed=64), "cdf53", 3).astype(np.int32))
+    for cfg in tile_configs():
+        for cc, wav in ((cg, "cdf97"), (cg.to(torch.bfloat16), "cdf97"), (cg, "cdf53f"), (ci, "cdf53")):
+            for lv in (1, 3):
+                say("semi-vector inverse", shape, cfg, wav, cc.dtype, lv)
+                even = back_pitched(d.dwt2_inv, cc, wav, lv, w + 2 if w % 4 == 0 else w, cfg)
+                odd = back_pitched(d.dwt2_inv, cc, wav, lv, w + 1, cfg)
+                assert torch.equal(even, odd), (cfg, wav, cc.dtype, lv)
+                assert torch.equal(even, d.inv(cc, wav, lv, config=cfg)), (cfg, wav, cc.dtype, lv)
+        say("semi-vector adjoint", shape, cfg)
+        even = back_pitched(d.dwt2_adj, cg, "cdf97", 3, w + 2 if w % 4 == 0 else w, cfg)
+        odd = back_pitched(d.dwt2_adj, cg, "cdf97", 3, w + 1, cfg)
+        assert torch.equal(even, odd), cfg
+        r = back_pitched(d.dwt2_inv, cg, "cdf97", 3, w + 2 if w % 4 == 0 else w, cfg)
+        assert rel_err(host(r), lifting.inv(c, "cdf97", 3)) <= TOL97, cfg
+
+
 def test_multilevel_graph_replay():
     """A 5-level forward + inverse of a plane stack (one launch per level,
     workspace from the graph's pool) captured in a graph and replayed with
