@@ -317,7 +317,8 @@ def test_precision_report_1024_5_levels(tdt, min_psnr):
     assert psnr >= min_psnr
 
 
-@pytest.mark.parametrize("shape,lv", [((3, 37, 53), 3), ((5, 260, 2056), 2), ((2, 2, 3000), 1)])
+@pytest.mark.parametrize("shape,lv", [((3, 37, 53), 3), ((5, 260, 2056), 2), ((2, 2, 3000), 1),
+                                      ((3, 300, 1030), 2)])
 def test_plane_batch_equals_single_planes(shape, lv):
     """A plane batch (one launch per level for all planes) equals the
     single-image transform of every plane, bit for bit, in every direction
