@@ -175,10 +175,18 @@ _DTYPE_NAMES = {DWT2_F32: "f32", DWT2_BF16: "bf16", DWT2_F16: "f16", DWT2_I32: "
 _DIRECTIONS = {"dwt2_fwd": "fwd", "dwt2_inv": "inv", "dwt2_adj": "adj"}
 
 
+_tuned = {}
+
+
 def tuned_config(direction: str, wavelet: str, dtype: int, h: int, w: int, levels: int):
-    """Kernel configuration the autotuner recorded for this case, or None."""
+    """Kernel configuration the autotuner recorded for this case, or None
+    (looked up once per case and size class: small transforms are bound by
+    the per-call host time)."""
     from . import autotune
-    return autotune.lookup(direction, wavelet, _DTYPE_NAMES[dtype], h, w, levels)
+    k = (direction, wavelet, dtype, autotune.size_class(h, w), levels)
+    if k not in _tuned:
+        _tuned[k] = autotune.lookup(direction, wavelet, _DTYPE_NAMES[dtype], h, w, levels)
+    return _tuned[k]
 
 
 def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=False, factored=False):

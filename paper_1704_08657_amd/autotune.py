@@ -33,10 +33,17 @@ def key(arch: str, direction: str, wavelet: str, dtype: str, h: int, w: int, lev
     return f"{arch}|{direction}|{wavelet}|{dtype}|{size_class(h, w)}|{levels}"
 
 
+_arch = None
+
+
 def arch_name() -> str:
-    import torch
-    p = torch.cuda.get_device_properties(0)
-    return getattr(p, "gcnArchName", p.name).split(":")[0]
+    """The GPU's architecture name (queried once per process)."""
+    global _arch
+    if _arch is None:
+        import torch
+        p = torch.cuda.get_device_properties(0)
+        _arch = getattr(p, "gcnArchName", p.name).split(":")[0]
+    return _arch
 
 
 _cache = None
@@ -81,6 +88,8 @@ def tune_case(direction: str, wavelet: str, dtype: str, h: int, w: int, levels: 
     global _cache
     _cache = dict(cache)
     _cache[key(arch_name(), direction, wavelet, dtype, h, w, levels)] = best
+    from . import _tuned               # the binding's memo of cache lookups
+    _tuned.clear()
     return best, times
 
 
