@@ -160,6 +160,8 @@ def _stream_ptr(x):
 
 def workspace(h: int, w: int, levels: int, dtype, device, planes: int = 1):
     """A workspace tensor for one call on `planes` h x w images (None if not needed)."""
+    if levels == 1:
+        return None                       # one level keeps no intermediate LL band
     torch = _torch()
     n = ctypes.c_size_t(0)
     st = lib().dwt2_workspace_bytes_planes(h, w, levels, dtype, planes, ctypes.byref(n))

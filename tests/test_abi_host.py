@@ -41,6 +41,12 @@ def test_max_levels_matches_oracle(h, w):
 def test_workspace_bytes():
     st, n = d.dwt2_workspace_bytes(512, 512, 1, d.DWT2_F32)
     assert st == 0 and n == 0
+    # one level never needs a workspace, for any plane count (the binding
+    # relies on it and skips the query)
+    for h, w, planes in [(2, 2, 1), (37, 53, 3), (4096, 4094, 1000)]:
+        m = ctypes.c_size_t(1)
+        assert d.lib().dwt2_workspace_bytes_planes(h, w, 1, d.DWT2_F32, planes, ctypes.byref(m)) == 0
+        assert m.value == 0
     st, n = d.dwt2_workspace_bytes(8192, 8192, 5, d.DWT2_F32)
     # LL of level 1 (4096 x 4096) and level 2 (2048 x 2048), pitch multiple of 64
     assert st == 0 and n == 4096 * 4096 * 4 + 2048 * 2048 * 4
