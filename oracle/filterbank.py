@@ -59,7 +59,8 @@ def half_band_Q(N: int) -> np.ndarray:
 
 def cdf_filters(name: str):
     """(h, g): analysis low-pass h (centred on an even sample) and high-pass g
-    (centred on an odd sample), normalised as the oracle's lifting form:
+    (centred on an odd sample), normalised as the oracle's lifting form
+    ("dd137": see dd137_filters):
     CDF 9/7 with DC gain sqrt(2) for both low-pass filters, "cdf53" (the real
     counterpart of the reversible integer transform, unscaled) with h DC gain
     1 and g = (-1/2, 1, -1/2), and "cdf53f" (the real-valued CDF 5/3 with the
@@ -74,6 +75,8 @@ def cdf_filters(name: str):
         h, f0 = h.real, f0.real
         h *= math.sqrt(2.0) / h.sum()
         f0 *= math.sqrt(2.0) / f0.sum()
+    elif name == "dd137":
+        return dd137_filters()
     elif name in ("cdf53", "cdf53f"):
         q = half_band_Q(2)                      # 1 + 2y
         h = _lp_mul(_c_term(), q[0] * np.array([0, 1.0, 0]) + q[1] * _y_minus(0.0).real)
@@ -85,6 +88,51 @@ def cdf_filters(name: str):
         raise ValueError(name)
     L = (len(f0) - 1) // 2
     g = f0 * np.array([(-1) ** abs(k) for k in range(-L, L + 1)])
+    return h, g
+
+
+def dd137_filters():
+    """(h, g) of the Deslauriers-Dubuc 13/7 wavelet, derived without lifting.
+
+    The synthesis low-pass is the 4-point Deslauriers-Dubuc interpolating
+    filter, the closed form c^2 Q_2(y) = c^2 (1 + 2y) (7 taps); the analysis
+    high-pass is its modulation.  The analysis low-pass h is the symmetric
+    13-tap filter for which the product h f0 is half-band (PR: every even
+    power of the product except z^0 vanishes), with a zero of order 4 at the
+    Nyquist frequency; both low-pass filters get DC gain sqrt(2)."""
+    q = half_band_Q(2)
+    f0 = _lp_mul(_lp_mul(_c_term(), _c_term()), q[0] * np.array([0, 1.0, 0]) + q[1] * _y_minus(0.0).real)
+    f0 *= math.sqrt(2.0) / f0.sum()
+    # unknowns: h[0..6] (h[-k] = h[k]); 7 linear conditions
+    L = 6
+    rows, rhs = [], []
+
+    def full(v):
+        return np.concatenate([v[:0:-1], v])            # h[-6..6] from h[0..6]
+
+    def prod_coeff(k):
+        """Row of the linear map h[0..6] -> coefficient of z^k in h f0."""
+        r = np.zeros(L + 1)
+        Lf = (len(f0) - 1) // 2
+        for j in range(-L, L + 1):
+            i = k - j
+            if -Lf <= i <= Lf:
+                r[abs(j)] += f0[i + Lf]
+        return r
+    for k in (2, 4, 6, 8):                              # half-band: even powers vanish
+        rows.append(prod_coeff(k))
+        rhs.append(0.0)
+    dc = np.array([1.0] + [2.0] * L)                    # sum of the taps
+    rows.append(dc)
+    rhs.append(math.sqrt(2.0))
+    alt = np.array([1.0] + [2.0 * (-1) ** k for k in range(1, L + 1)])
+    rows.append(alt)                                    # H(-1) = 0
+    rhs.append(0.0)
+    rows.append(np.array([0.0] + [2.0 * (-1) ** k * k * k for k in range(1, L + 1)]))
+    rhs.append(0.0)                                     # H''(-1) = 0 (odd orders vanish by symmetry)
+    h = full(np.linalg.solve(np.array(rows), np.array(rhs)))
+    Lg = (len(f0) - 1) // 2
+    g = f0 * np.array([(-1) ** abs(k) for k in range(-Lg, Lg + 1)])
     return h, g
 
 

@@ -70,7 +70,7 @@ import numpy as np
 
 # Daubechies-Sweldens lifting factorisation of the CDF 9/7 filter pair
 # (predict, update, predict, update).  Pinned against the closed-form filters
-# in tests/test_oracle_filters.py.
+# by test_cdf97_constants_from_closed_form in tests/test_oracle_pins.py.
 ALPHA = -1.586134342059924
 BETA = -0.052980118572961
 GAMMA = 0.882911075530934
@@ -84,18 +84,40 @@ P53 = -0.5
 U53 = 0.25
 ZETA53 = math.sqrt(2.0) / (1.0 + 2.0 * U53 * (1.0 + 2.0 * P53))
 
+# Deslauriers-Dubuc 13/7 (the paper's third wavelet, Section "Evaluation"):
+# one pair of 4-tap steps, the 4-point interpolating predict and its update,
+#     odd[m]  -= (9 (even[m] + even[m+1]) - (even[m-1] + even[m+2])) / 16
+#     even[m] += (9 (odd[m-1] + odd[m]) - (odd[m-2] + odd[m+1])) / 32
+# as {offset: coefficient} taps (offset k reads sample m + k).
+DD137_P = {-1: 1.0 / 16, 0: -9.0 / 16, 1: -9.0 / 16, 2: 1.0 / 16}
+DD137_U = {-2: -1.0 / 32, -1: 9.0 / 32, 0: 9.0 / 32, 1: -1.0 / 32}
+# The same normalisation rule (low-pass DC gain sqrt(2) per axis): the
+# predict removes constants (its taps sum to -1), so the lifted low-pass has
+# DC gain 1 and zeta = sqrt(2): LL * 2, HH * 1/2.
+ZETA137 = math.sqrt(2.0) / (1.0 + sum(DD137_U.values()) * (1.0 + sum(DD137_P.values())))
+
 # "cdf53" is the reversible integer transform, "cdf53f" the real-valued one
-WAVELETS = ("cdf97", "cdf53", "cdf53f")
+WAVELETS = ("cdf97", "cdf53", "cdf53f", "dd137")
 INT_LIMIT = 1 << 28
 
 
 def lifting_pairs(wavelet: str):
-    """(p, u) per lifting pair of the float wavelet (eq. (2), K pairs)."""
+    """(p, u) per lifting pair of a two-tap float wavelet (eq. (2), K pairs):
+    P(z) = p (1 + z), U(z) = u (1 + z^-1)."""
     if wavelet == "cdf97":
         return [(ALPHA, BETA), (GAMMA, DELTA)]
     if wavelet == "cdf53f":
         return [(P53, U53)]
-    raise ValueError(f"no float lifting pairs for {wavelet!r}")
+    raise ValueError(f"no two-tap float lifting pairs for {wavelet!r}")
+
+
+def lifting_taps(wavelet: str):
+    """[(P, U), ...] per lifting pair of any float wavelet, each filter as
+    {offset: coefficient}: odd[m] += sum_k P[k] even[m+k],
+    even[m] += sum_k U[k] odd[m+k]."""
+    if wavelet == "dd137":
+        return [(dict(DD137_P), dict(DD137_U))]
+    return [({0: p, 1: p}, {-1: u, 0: u}) for p, u in lifting_pairs(wavelet)]
 
 
 def zeta(wavelet: str) -> float:
@@ -104,6 +126,8 @@ def zeta(wavelet: str) -> float:
         return ZETA
     if wavelet == "cdf53f":
         return ZETA53
+    if wavelet == "dd137":
+        return ZETA137
     raise ValueError(f"no scaling for {wavelet!r}")
 
 
@@ -192,6 +216,63 @@ def _update(odd, even, u, axis, integer, sign=+1):
 H_AXIS, V_AXIS = 1, 0
 
 
+# ---------------------------------------------------------------------------
+# lifting steps with taps beyond the nearest neighbours (DD 13/7)
+# ---------------------------------------------------------------------------
+# With longer filters the symmetric extension is no longer a clamp of the
+# component index: the sample two places before the first even sample is the
+# second even sample (X[-2] = X[2]).  The general rule reflects the pixel
+# position 2k + q of component sample k (q = 0 even, 1 odd) into [0, n) and
+# maps it back; a reflection keeps the parity of the position, so the sample
+# read is always one of the same component.
+
+def reflect_component(k: np.ndarray, q: int, n: int) -> np.ndarray:
+    """Component index of sample k (any integer) of the parity-q component of
+    a length-n signal under whole-point symmetric extension."""
+    p = 2 * np.asarray(k) + q
+    if n == 1:
+        return np.zeros_like(p)
+    period = 2 * (n - 1)
+    p = np.mod(p, period)
+    p = np.where(p > n - 1, period - p, p)
+    assert np.all(p % 2 == q)
+    return (p - q) // 2
+
+
+def _lift_taps(src, dst, taps, axis, n, q_src, sign=+1):
+    """dst[m] += sign * sum_k taps[k] * src[m + k] along `axis`, the source
+    (a component of parity q_src of a length-n signal) read through the
+    symmetric extension."""
+    m = np.arange(dst.shape[axis])
+    for k, c in sorted(taps.items()):
+        dst += (sign * c) * np.take(src, reflect_component(m + k, q_src, n), axis=axis)
+
+
+def _forward_pair_taps(x, P, U, h, w):
+    x0, x1, x2, x3 = x
+    # T_P^H, T_P^V, S_U^H, S_U^V (the order of the two-tap pairs)
+    _lift_taps(x0, x1, P, H_AXIS, w, 0)
+    _lift_taps(x2, x3, P, H_AXIS, w, 0)
+    _lift_taps(x0, x2, P, V_AXIS, h, 0)
+    _lift_taps(x1, x3, P, V_AXIS, h, 0)
+    _lift_taps(x1, x0, U, H_AXIS, w, 1)
+    _lift_taps(x3, x2, U, H_AXIS, w, 1)
+    _lift_taps(x2, x0, U, V_AXIS, h, 1)
+    _lift_taps(x3, x1, U, V_AXIS, h, 1)
+
+
+def _inverse_pair_taps(x, P, U, h, w):
+    x0, x1, x2, x3 = x
+    _lift_taps(x2, x0, U, V_AXIS, h, 1, sign=-1)
+    _lift_taps(x3, x1, U, V_AXIS, h, 1, sign=-1)
+    _lift_taps(x1, x0, U, H_AXIS, w, 1, sign=-1)
+    _lift_taps(x3, x2, U, H_AXIS, w, 1, sign=-1)
+    _lift_taps(x0, x2, P, V_AXIS, h, 0, sign=-1)
+    _lift_taps(x1, x3, P, V_AXIS, h, 0, sign=-1)
+    _lift_taps(x0, x1, P, H_AXIS, w, 0, sign=-1)
+    _lift_taps(x2, x3, P, H_AXIS, w, 0, sign=-1)
+
+
 def _forward_pair(x, p, u, integer):
     x0, x1, x2, x3 = x
     # T_P^H
@@ -248,8 +329,12 @@ def fwd_level(X: np.ndarray, wavelet: str) -> np.ndarray:
         raise ValueError("every transformed level must be at least 2 x 2")
     integer = is_integer(wavelet)
     x = split(X)
-    for p, u in _pairs(wavelet):
-        _forward_pair(x, p, u, integer)
+    if wavelet == "dd137":
+        for P, U in lifting_taps(wavelet):
+            _forward_pair_taps(x, P, U, h, w)
+    else:
+        for p, u in _pairs(wavelet):
+            _forward_pair(x, p, u, integer)
     x0, x1, x2, x3 = x
     if not integer:
         z = zeta(wavelet)
@@ -269,8 +354,12 @@ def inv_level(Y: np.ndarray, wavelet: str) -> np.ndarray:
         z = zeta(wavelet)
         x[0] *= 1.0 / (z * z)
         x[3] *= z * z
-    for p, u in reversed(_pairs(wavelet)):
-        _inverse_pair(x, p, u, integer)
+    if wavelet == "dd137":
+        for P, U in reversed(lifting_taps(wavelet)):
+            _inverse_pair_taps(x, P, U, h, w)
+    else:
+        for p, u in reversed(_pairs(wavelet)):
+            _inverse_pair(x, p, u, integer)
     return merge(*x, h, w)
 
 

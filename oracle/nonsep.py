@@ -32,7 +32,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .lifting import lifting_pairs, is_integer, quadrants, split, zeta
+from .lifting import is_integer, lifting_pairs, merge, quadrants, split, zeta
 
 
 def nb(a: np.ndarray, dn: int, dm: int, shape) -> np.ndarray:
@@ -167,3 +167,191 @@ def nonsep_fwd_level(X: np.ndarray, wavelet: str = "cdf97", split_consts: bool =
     x[0] = x[0] * z ** 2
     x[3] = x[3] * z ** -2
     return quadrants(*x, h, w)
+
+
+# --------------------------------------------------------------------------
+# schemes written as 4x4 step matrices, evaluated on the symmetrically
+# extended image: the non-separable polyconvolution N_{P,U}, and the fused
+# lifting steps T_P, S_U with filters of any length (DD 13/7)
+# --------------------------------------------------------------------------
+# A matrix entry G*(z_n) H(z_m) -- a vertical 1-D filter times a horizontal
+# one -- is the pair (vertical taps, horizontal taps); taps are
+# {offset: coefficient}, offset k reading sample n + k (m + k).  ONE is the
+# unit filter.  The image is extended by the whole-point symmetric extension
+# (wide enough for every step's reach), split into its four polyphase
+# components, every step applied to whole planes with no border rule at all,
+# and the image's part cut out: lifting on the extended signal equals the
+# oracle's per-step reflection inside the image.
+
+ONE = {0: 1.0}
+
+
+def _compose(a: dict, b: dict) -> dict:
+    """The filter a b (apply b, then a): offsets add."""
+    out = {}
+    for i, x in a.items():
+        for j, y in b.items():
+            out[i + j] = out.get(i + j, 0.0) + x * y
+    return out
+
+
+def _plus(a: dict, b: dict) -> dict:
+    out = dict(a)
+    for k, v in b.items():
+        out[k] = out.get(k, 0.0) + v
+    return out
+
+
+def _neg(a: dict) -> dict:
+    return {k: -v for k, v in a.items()}
+
+
+def polyconv_matrix(P: dict, U: dict):
+    """N_{P,U} of Section "Proposed Schemes" (one lifting pair in one step):
+
+        [ V*V  V*U  U*V  U*U ]
+        [ V*P  V*   U*P  U*  ]      V = P U + 1
+        [ P*V  P*U  V    U   ]
+        [ P*P  P*   P    1   ]
+
+    as (vertical, horizontal) filter pairs, rows = output component."""
+    V = _plus(_compose(P, U), ONE)
+    return [[(V, V), (V, U), (U, V), (U, U)],
+            [(V, P), (V, ONE), (U, P), (U, ONE)],
+            [(P, V), (P, U), (ONE, V), (ONE, U)],
+            [(P, P), (P, ONE), (ONE, P), (ONE, ONE)]]
+
+
+def polyconv_inverse_matrix(P: dict, U: dict):
+    """The inverse of N_{P,U}: per axis the inverse of the pair matrix
+    [[V, U], [P, 1]] is [[1, -U], [-P, V]] (determinant V - U P = 1), and the
+    2-D matrix is again the product of the vertical and horizontal ones."""
+    V = _plus(_compose(P, U), ONE)
+    m1 = [[ONE, _neg(U)], [_neg(P), V]]
+    return [[(m1[c >> 1][k >> 1], m1[c & 1][k & 1]) for k in range(4)] for c in range(4)]
+
+
+def fused_T_matrix(P: dict):
+    """T_P of Section "Proposed Schemes" (None: no term; the diagonal is 1)."""
+    return [[(ONE, ONE), None, None, None],
+            [(ONE, P), (ONE, ONE), None, None],
+            [(P, ONE), None, (ONE, ONE), None],
+            [(P, P), (P, ONE), (ONE, P), (ONE, ONE)]]
+
+
+def fused_S_matrix(U: dict):
+    """S_U of Section "Proposed Schemes"."""
+    return [[(ONE, ONE), (ONE, U), (U, ONE), (U, U)],
+            [None, (ONE, ONE), None, (U, ONE)],
+            [None, None, (ONE, ONE), (ONE, U)],
+            [None, None, None, (ONE, ONE)]]
+
+
+def apply_matrix(x, M):
+    """One step: out_c = sum_k M[c][k] x_k over whole planes of equal shape.
+    Samples near the planes' edges read wrapped-around values; the callers'
+    margins keep that garbage outside the image."""
+    out = []
+    for c in range(4):
+        acc = np.zeros_like(x[0])
+        for k in range(4):
+            if M[c][k] is None:
+                continue
+            vt, ht = M[c][k]
+            for i, a in vt.items():
+                for j, b in ht.items():
+                    acc += (a * b) * np.roll(x[k], (-i, -j), axis=(0, 1))
+        out.append(acc)
+    return out
+
+
+def _reach(M) -> int:
+    return max(abs(k) for row in M for e in row if e is not None for t in e for k in t)
+
+
+def _extended_components(X: np.ndarray, margin: int):
+    """The four polyphase components of X extended symmetrically by `margin`
+    blocks on every side (one more sample at the end of an odd side, so that
+    all four components have the same shape); block (n, m) of a component
+    is block (n - margin, m - margin) of the image's."""
+    from .filterbank import wps_index
+    h, w = X.shape
+    rows = wps_index(np.arange(-2 * margin, h + 2 * margin + h % 2), h)
+    cols = wps_index(np.arange(-2 * margin, w + 2 * margin + w % 2), w)
+    return list(split(np.asarray(X, dtype=np.float64)[np.ix_(rows, cols)]))
+
+
+def _cut(x, margin: int, h: int, w: int):
+    he, ho, we, wo = (h + 1) // 2, h // 2, (w + 1) // 2, w // 2
+    sl = lambda n, m: (slice(margin, margin + n), slice(margin, margin + m))
+    return [x[0][sl(he, we)], x[1][sl(he, wo)], x[2][sl(ho, we)], x[3][sl(ho, wo)]]
+
+
+def matrix_scheme_fwd_level(X: np.ndarray, wavelet: str, scheme: str) -> np.ndarray:
+    """One forward scale of a float wavelet, every lifting pair applied as
+    one polyconvolution step N_{P,U} (scheme "polyconv") or as the two fused
+    steps T_P then S_U (scheme "fused"), on the extended image."""
+    from .lifting import lifting_taps
+    h, w = X.shape
+    pairs = lifting_taps(wavelet)
+    if scheme == "polyconv":
+        steps = [polyconv_matrix(P, U) for P, U in pairs]
+    elif scheme == "fused":
+        steps = [M for P, U in pairs for M in (fused_T_matrix(P), fused_S_matrix(U))]
+    else:
+        raise ValueError(scheme)
+    margin = sum(_reach(M) for M in steps) + 2
+    x = _extended_components(X, margin)
+    for M in steps:
+        x = apply_matrix(x, M)
+    x = _cut(x, margin, h, w)
+    z = zeta(wavelet)
+    x[0] = x[0] * z ** 2
+    x[3] = x[3] * z ** -2
+    return quadrants(*x, h, w)
+
+
+def matrix_scheme_inv_level(Y: np.ndarray, wavelet: str, scheme: str = "polyconv") -> np.ndarray:
+    """One inverse scale: the inverse polyconvolution of every pair, last
+    pair first, on the symmetric extension of the image the pyramid level
+    belongs to.  The extension of a subband is taken at the reflected pixel
+    position of each of its samples, the same extension the forward
+    transform of the extended image has."""
+    from .filterbank import wps_index
+    from .lifting import lifting_taps, unquadrants
+    if scheme != "polyconv":
+        raise ValueError(scheme)
+    h, w = Y.shape
+    steps = [polyconv_inverse_matrix(P, U) for P, U in reversed(lifting_taps(wavelet))]
+    margin = sum(_reach(M) for M in steps) + 2
+    q = list(unquadrants(np.asarray(Y, dtype=np.float64)))
+    z = zeta(wavelet)
+    q[0] = q[0] * z ** -2
+    q[3] = q[3] * z ** 2
+    x = []
+    for k in range(4):
+        pr, pc = k >> 1, k & 1
+        r = (wps_index(2 * np.arange(-margin, (h + 1) // 2 + margin) + pr, h) - pr) // 2
+        c = (wps_index(2 * np.arange(-margin, (w + 1) // 2 + margin) + pc, w) - pc) // 2
+        x.append(q[k][np.ix_(r, c)])
+    for M in steps:
+        x = apply_matrix(x, M)
+    return merge(*_cut(x, margin, h, w), h, w)
+
+
+def polyconv_fwd(X: np.ndarray, wavelet: str = "cdf97", levels: int = 1) -> np.ndarray:
+    """Multi-level forward transform with the polyconvolution scheme."""
+    from .lifting import level_shapes
+    Y = np.asarray(X, dtype=np.float64).copy()
+    for h, w in level_shapes(*Y.shape, levels):
+        Y[:h, :w] = matrix_scheme_fwd_level(Y[:h, :w], wavelet, "polyconv")
+    return Y
+
+
+def polyconv_inv(Y: np.ndarray, wavelet: str = "cdf97", levels: int = 1) -> np.ndarray:
+    """Multi-level inverse with the inverse polyconvolution scheme."""
+    from .lifting import level_shapes
+    X = np.asarray(Y, dtype=np.float64).copy()
+    for h, w in reversed(level_shapes(*X.shape, levels)):
+        X[:h, :w] = matrix_scheme_inv_level(X[:h, :w], wavelet)
+    return X

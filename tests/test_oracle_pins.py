@@ -250,7 +250,10 @@ def test_appendix_predict_example():
 # ---------------------------------------------------------------- P6 ------
 @pytest.mark.parametrize("shape", [(2, 2), (2, 3), (3, 2), (6, 8), (7, 9), (33, 66), (128, 130)])
 def test_separable_equals_nonseparable(shape):
-    """'The proposed schemes compute the same values as the original ones.'"""
+    """Section "Proposed Schemes": the fused non-separable steps (plain and
+    with the P0/P1 split of Section "Optimization Approach") reach exactly the
+    coefficients of the separable lifting scheme; pinned here to FP64
+    rounding for the real wavelets and bit for bit for the integer 5/3."""
     rng = np.random.default_rng(3)
     X = rng.random(shape)
     ref = lifting.fwd(X, "cdf97", 1)
@@ -418,3 +421,140 @@ def mask_interior(H, W, r0, r1, c0, c1, m):
     if c1 < W:
         okc &= c1 - cols >= m
     return np.outer(okr, okc)
+
+
+# ------------------------------------------------- DD 13/7 (Section "Evaluation")
+@pytest.mark.parametrize("h", [2, 3, 4, 5, 7, 9, 12, 17, 24, 31, 40])
+def test_dd137_perfect_reconstruction(h):
+    rng = np.random.default_rng(100 + h)
+    for w in [2, 3, 4, 6, 7, 11, 16, 25, 33, 40]:
+        X = rng.random((h, w))
+        for levels in sorted({1, lifting.max_levels(h, w)}):
+            Y = lifting.fwd(X, "dd137", levels)
+            assert np.abs(lifting.inv(Y, "dd137", levels) - X).max() < 1e-13
+
+
+def test_dd137_closed_form_filters():
+    """The analysis pair derived without lifting (synthesis low-pass = the
+    4-point Deslauriers-Dubuc interpolator c^2 (1 + 2y); analysis low-pass =
+    the symmetric 13-tap solution of the biorthogonality conditions) is the
+    published 13/7 pair: h = (-1, 0, 18, -16, -63, 144, 348, ...) / 512 and
+    g = (1, 0, -9, 16, -9, 0, 1) / 16, each scaled by the DC-gain rule."""
+    h, g = filterbank.cdf_filters("dd137")
+    z = lifting.ZETA137
+    assert z == pytest.approx(math.sqrt(2.0), abs=1e-15)
+    hh = np.array([-1, 0, 18, -16, -63, 144, 348, 144, -63, -16, 18, 0, -1]) / 512.0
+    gg = np.array([1, 0, -9, 16, -9, 0, 1]) / 16.0
+    assert np.abs(h - z * hh).max() < 1e-14
+    assert np.abs(g - gg / z).max() < 1e-14
+    # the product of the analysis and synthesis low-pass filters is half-band
+    f0 = np.abs(gg) * np.array([-1, 1, 1, 1, 1, 1, -1])
+    prod = np.convolve(hh, f0)
+    c = (len(prod) - 1) // 2
+    even = [prod[c + k] for k in range(-c, c + 1) if k % 2 == 0 and k != 0]
+    assert np.abs(even).max() < 1e-15 and prod[c] == pytest.approx(1.0)
+
+
+def test_dd137_lifting_equals_closed_form_filter_bank():
+    """One DD 13/7 scale equals separable convolution with the closed-form
+    13/7 filters on the symmetrically extended image, for every length 2..39
+    (the 4-tap steps read two samples across a border: the extension is a
+    reflection of the pixel position, not a clamp of the component index)."""
+    rng = np.random.default_rng(8)
+    for n in range(2, 40):
+        X = rng.random((2, n))
+        assert rel_err(lifting.fwd(X, "dd137"), filterbank.separable_bank(X, "dd137")) < 1e-13
+        X = rng.random((n, 3))
+        assert rel_err(lifting.fwd(X, "dd137"), filterbank.separable_bank(X, "dd137")) < 1e-13
+
+
+def test_dd137_constant_and_polynomial_images():
+    """Constant images: LL = 2c per level, no detail anywhere.  Images of
+    degree <= 3 in each axis (the 4-point interpolating predict is exact for
+    cubics): zero details more than 6 pixels from the borders; a degree-4
+    term is not annihilated (the pin is sharp)."""
+    X = np.full((40, 46), 0.75)
+    Y = lifting.fwd(X, "dd137", 3)
+    for lv, b, r0, r1, c0, c1 in window.band_boxes(40, 46, 3):
+        blk = Y[r0:r1, c0:c1]
+        assert np.abs(blk - (0.75 * 8 if b == "LL" else 0.0)).max() < 1e-13
+    H, W = 72, 80
+    i = np.arange(H)[:, None] / H
+    j = np.arange(W)[None, :] / W
+    X = 1 + 2 * i - 3 * i ** 2 + 0.5 * i ** 3 + j ** 3 - 0.7 * j + i * j ** 2 + (i ** 3) * (j ** 3)
+    Y = lifting.fwd(X, "dd137", 1)
+    he, we = H // 2, W // 2
+    m = 4
+    for blk in (Y[m:he - m, we + m:W - m], Y[he + m:H - m, m:we - m], Y[he + m:H - m, we + m:W - m]):
+        assert np.abs(blk).max() < 1e-12
+    Y4 = lifting.fwd(X + j ** 4, "dd137", 1)
+    assert np.abs(Y4[m:he - m, we + m:W - m]).max() > 1e-9
+
+
+# ------------------------------------ non-separable polyconvolution N_{P,U}
+@pytest.mark.parametrize("wav", ["cdf97", "cdf53f", "dd137"])
+def test_matrix_schemes_equal_separable(wav):
+    """Section "Proposed Schemes": one polyconvolution step N_{P,U} per
+    lifting pair, and the fused steps T_P, S_U (for DD 13/7 with 4-tap
+    filters), evaluated on the symmetrically extended image, reach the
+    separable lifting's coefficients (FP64 rounding), on shapes with odd and
+    even sides down to 2 x 2; the inverse polyconvolution restores the image."""
+    rng = np.random.default_rng(9)
+    for h in (2, 3, 4, 5, 8, 13, 21, 34):
+        for w in (2, 3, 6, 7, 16, 19, 30):
+            X = rng.random((h, w))
+            ref = lifting.fwd_level(X, wav)
+            assert rel_err(nonsep.matrix_scheme_fwd_level(X, wav, "polyconv"), ref) < 1e-14
+            assert rel_err(nonsep.matrix_scheme_fwd_level(X, wav, "fused"), ref) < 1e-14
+            assert np.abs(nonsep.matrix_scheme_inv_level(ref, wav) - X).max() < 1e-13
+    X = rng.random((67, 130))
+    lv = 5
+    ref = lifting.fwd(X, wav, lv)
+    assert rel_err(nonsep.polyconv_fwd(X, wav, lv), ref) < 1e-14
+    assert np.abs(nonsep.polyconv_inv(ref, wav, lv) - X).max() < 1e-12
+
+
+def test_polyconv_matrix_equals_symbolic_product():
+    """The numeric N_{P,U} used by the oracle equals the exact symbolic
+    product S_U T_P (polymat, with V = P U + 1) for both CDF 9/7 pairs and
+    the CDF 5/3 pair: every entry, as a 2-D kernel."""
+    from fractions import Fraction
+    for wav in ("cdf97", "cdf53f"):
+        for (P, U), (p, u) in zip(lifting.lifting_taps(wav), lifting.lifting_pairs(wav)):
+            Ps = polymat.horizontal([(0, Fraction(p)), (1, Fraction(p))])
+            Us = polymat.horizontal([(0, Fraction(u)), (-1, Fraction(u))])
+            exact = polymat.matmul(polymat.S_fused(Us), polymat.T_fused(Ps))
+            assert polymat.equal(exact, polymat.N_polyconv(Ps, Us))
+            M = nonsep.polyconv_matrix(P, U)
+            for r in range(4):
+                for c in range(4):
+                    vt, ht = M[r][c]
+                    num = {}
+                    for i, a in vt.items():
+                        for j, b in ht.items():
+                            num[(j, i)] = num.get((j, i), 0.0) + a * b
+                    num = {k: v for k, v in num.items() if v != 0.0}
+                    sym = {k: float(v) for k, v in exact[r][c].items()}
+                    assert set(num) == set(sym), (wav, r, c)
+                    assert max(abs(num[k] - sym[k]) for k in sym) < 1e-15
+
+
+def test_polyconv_pixel_footprints():
+    """For the CDF wavelets one polyconvolution step reads, per output
+    component, a pixel footprint of 5 x 5 (LL), 5 x 3 (HL), 3 x 5 (LH) and
+    3 x 3 (HH) samples (rows x columns), the filter sizes Section "Proposed
+    Schemes" gives for N_{P,U}."""
+    (P, U), _ = lifting.lifting_taps("cdf97")
+    M = nonsep.polyconv_matrix(P, U)
+    for c, want in zip(range(4), [(5, 5), (5, 3), (3, 5), (3, 3)]):
+        rows, cols = set(), set()
+        for k in range(4):
+            vt, ht = M[c][k]
+            # input component k = (row parity, column parity) at block offset
+            # (i, j) sits at pixel offset (2 i + pk - pc) from the output pixel
+            for i in vt:
+                rows.add(2 * i + (k >> 1) - (c >> 1))
+            for j in ht:
+                cols.add(2 * j + (k & 1) - (c & 1))
+        assert (max(rows) - min(rows) + 1, max(cols) - min(cols) + 1) == want
+        assert rows == set(range(min(rows), max(rows) + 1)) and cols == set(range(min(cols), max(cols) + 1))
