@@ -134,6 +134,18 @@ def per_launch_sample(torch, fn, n):
     return [a.elapsed_time(b) for a, b in zip(starts, ends)]
 
 
+def cpu_model():
+    """The host CPU's model name (first 'model name' line of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(x, seconds):
     """The CPU oracle (FP64 NumPy separable lifting, one core) on a 2048 x 2048
     crop of the benchmark image, repeated for about `seconds`."""
@@ -148,7 +160,8 @@ def cpu_baseline(x, seconds):
         if el >= seconds:
             break
     gpx = n * crop.size / el / 1e9
-    return {"value": gpx, "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
+    return {"value": gpx, "unit": "Gpixel/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(),
             "sample": f"{n} x CDF 9/7 fwd 1 level on the 2048x2048 top-left crop of the same "
                       f"image, FP64 NumPy, single thread, {el:.1f} s"}
 
@@ -180,7 +193,8 @@ def cpu_pool_baseline():
         "planes: 192 x 1024^2 (64 x 3), 3 levels": [(1024, 1024, 200 + k, 3) for k in range(192)],
     }
     ctx = mp.get_context("fork")
-    with ctx.Pool(workers) as pool:
+    pool = ctx.Pool(workers)
+    try:
         for name, jobs in samples.items():
             t0 = time.perf_counter()
             res = pool.map(_pool_job, jobs, chunksize=1)
@@ -188,8 +202,42 @@ def cpu_pool_baseline():
             px = sum(r[0] for r in res)
             out[name] = {"value": px / el / 1e9, "unit": "Gpixel/s", "seconds": round(el, 2),
                          "pixels": px, "busy_seconds": round(sum(r[1] for r in res), 2)}
-    return {"cores": workers, "kind": "oracle", "method": "multiprocessing pool, one image per task, "
+    finally:
+        # wait for every worker to exit before the GPU is touched, so that
+        # no process outlives the benchmark
+        pool.close()
+        pool.join()
+    for child in mp.active_children():
+        child.join(5)
+    return {"cores": workers, "kind": "oracle", "cpu_model": cpu_model(),
+            "method": "multiprocessing pool, one image per task, "
             "FP64 NumPy; wall time includes generating each input in its worker", "samples": out}
+
+
+def oracle_precision_errors(saved):
+    """Coefficient errors of the precision forms against the FP64 oracle (the
+    CPU leg of the benchmark, after the GPU timing): for every saved plane,
+    the oracle's 5-level forward of the storage-rounded input on the nine
+    probe crops (corners, edge midpoints, centre), compared over the crops'
+    exactly evaluated part with the GPU's coefficients.  Returns per form the
+    largest |gpu - oracle|, the largest |coefficient| and their ratio."""
+    from oracle import lifting, window
+    out = {}
+    for name, (planes_in, planes_coef, lv) in saved.items():
+        worst, scale, crops = 0.0, 0.0, 0
+        for xp, cp in zip(planes_in, planes_coef):
+            H, W = xp.shape
+            scale = max(scale, float(np.abs(cp).max()))
+            m = window.default_margin(lv)
+            for r0, r1, c0, c1 in window.probe_crops(H, W, lv, size=256):
+                sub = lifting.fwd(xp[r0:r1, c0:c1].astype(np.float64), "cdf97", lv)
+                cut = window.crop_pyramid(cp, lv, r0, r1, c0, c1)
+                mask = window.crop_valid_mask(H, W, lv, r0, r1, c0, c1, m)
+                worst = max(worst, float(np.abs(cut[mask].astype(np.float64) - sub[mask]).max()))
+                crops += 1
+        out[name] = {"coeff_max_abs_vs_fp64_oracle": worst, "max_abs_coeff": scale,
+                     "coeff_max_abs_rel": worst / scale if scale else None, "oracle_crops": crops}
+    return out
 
 
 def main():
@@ -262,6 +310,7 @@ def main():
     roofline["of_copy"] = round(achieved / copy_ref["GB/s"], 4)
 
     forms = []
+    precision_saved = {}
 
     def want(name):
         return args.only is None or re.search(args.only, name) is not None
@@ -286,6 +335,12 @@ def main():
              tune_key=None)
         form("cdf97 inv f32 1 level", lambda i, c: d.inv(ys[i % pairs], "cdf97", 1, out=xs[i % pairs], config=c),
              1, 4, tune_key=("inv", "cdf97", "f32"))
+        # the hand-written adjoint W^T (transposed fused steps in reverse
+        # order, transposed border weights): same bytes as the forward
+        form("cdf97 adj f32 1 level", lambda i, c: d.adj(ys[i % pairs], 1, out=xs[i % pairs], config=c),
+             1, 4, tune_key=("adj", "cdf97", "f32"))
+        form("cdf97 adj f32 5 levels", lambda i, c: d.adj(ys[i % pairs], 5, out=xs[i % pairs], config=c),
+             5, 4, tune_key=("adj", "cdf97", "f32"))
         # the separable comparison scheme (8 steps and barriers per level
         # instead of 4), same tile configuration as the fused forms
         form("cdf97 fwd f32 1 level separable (8 barriers)",
@@ -387,15 +442,15 @@ def main():
         sized_form("cdf97 fwd f32 5 levels, 16384^2", 16384, 5, 2, steps=20)
 
         # precision: 3 x 8192^2 planes (seed 3), 5-level forward + inverse per
-        # step, FP32 / BF16 / FP16 storage.  Errors of the 16-bit forms are
-        # taken against the FP32-storage transform of the same rounded input
-        # (which the parity tests hold within 1e-5 of the FP64 oracle) and,
-        # for the reconstruction, against the rounded input and the FP32
-        # original (PSNR with peak 1.0).
+        # step, FP32 / BF16 / FP16 storage.  The reconstruction is compared
+        # on the GPU with the storage-rounded input and with the FP32
+        # original (PSNR with peak 1.0); the coefficients are compared with
+        # the FP64 oracle of the storage-rounded input by the CPU leg below
+        # (probe crops of every plane), so the inputs and coefficients are
+        # kept on the host until then.
         x3 = (torch.from_numpy(workloads.planes(3, N, N, seed=3)).to(dev)
               if any(want(f"cdf97 fwd+inv {nm} 5 levels, 3 x {N}^2 planes") for nm in ("f32", "bf16", "f16"))
               else None)
-        c32 = None
         for tdt, nm in [(torch.float32, "f32"), (torch.bfloat16, "bf16"), (torch.float16, "f16")]:
             if not want(f"cdf97 fwd+inv {nm} 5 levels, 3 x {N}^2 planes"):
                 continue
@@ -415,19 +470,15 @@ def main():
                      "hbm_frac": round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
             fwd_inv(0)
             torch.cuda.synchronize()
-            ref = d.fwd(xq.float(), "cdf97", 5)
-            if tdt == torch.float32:
-                c32 = ref
-            err = (cq.float() - ref).abs().max().item()
-            entry["coeff_max_abs_vs_fp32_storage"] = err
-            entry["coeff_max_abs_rel"] = err / ref.abs().max().item()
             for tag, base in (("rounded_input", xq.float()), ("fp32_original", x3)):
-                mse = ((rq.float() - base) ** 2).mean().item()
+                mse = ((rq.double() - base.double()) ** 2).mean().item()
                 entry[f"psnr_db_vs_{tag}"] = round(10 * np.log10(1.0 / mse), 2) if mse > 0 else None
+            precision_saved[entry["form"]] = ([xq[p].double().cpu().numpy() for p in range(3)],
+                                              [cq[p].float().cpu().numpy() for p in range(3)], 5)
             forms.append(entry)
-            del xq, cq, rq, ref
+            del xq, cq, rq
             torch.cuda.empty_cache()
-        del x3, c32
+        del x3
         torch.cuda.empty_cache()
 
         # differentiation: 64 x 3 x 1024^2 FP32 (seed 4), 3-level forward via
@@ -448,10 +499,21 @@ def main():
             xa.grad = None
         if want(ag_name):
             _, ms = time_steps(torch, train_step, 10, 2)
-            ab = 2 * 64 * 3 * algorithmic_bytes(1024, 1024, 3, 4)
+            # the two transforms of the step alone (forward of the stack,
+            # adjoint of a cotangent of the same shape), timed the same way;
+            # the rest of the step is PyTorch's loss and its gradient
+            xd = xa.detach()
+            ya = torch.empty_like(xd)
+            ga = torch.empty_like(xd)
+            _, fms = time_steps(torch, lambda i: d.fwd(xd, "cdf97", 3, out=ya), 10, 2)
+            _, ams = time_steps(torch, lambda i: d.adj(ya, 3, out=ga), 10, 2)
+            ab1 = 64 * 3 * algorithmic_bytes(1024, 1024, 3, 4)
             forms.append({"form": ag_name,
                           "Gpixel/s": round(64 * 3 * 1024 * 1024 / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
-                          "transform_GB/s": round(ab / (ms * 1e-3) / 1e9, 1)})
+                          "forward_ms": round(fms, 4), "forward_hbm_frac": round(ab1 / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "adjoint_ms": round(ams, 4), "adjoint_hbm_frac": round(ab1 / (ams * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "loss_and_other_ms": round(ms - fms - ams, 4)})
+            del xd, ya, ga
         del xa, tgt
         torch.cuda.empty_cache()
 
@@ -505,6 +567,12 @@ def main():
     cpu = None if args.no_cpu else cpu_baseline(x_host, args.cpu_seconds)
     if cpu is not None:
         cpu["pool"] = pool
+        # the CPU leg also checks the precision forms against the FP64 oracle
+        errs = oracle_precision_errors(precision_saved)
+        for f in forms:
+            if f["form"] in errs:
+                f.update(errs[f["form"]])
+    precision_saved.clear()
 
     line = {
         "metric": "Gpixel/s 2-D CDF 9/7 fwd 8192^2 FP32 (+ % HBM roofline)",

@@ -163,9 +163,16 @@ int dwt2_fwd(const void* src, void* dst, int32_t height, int32_t width,
              unsigned flags, void* workspace, size_t workspace_bytes,
              void* stream);
 
-/* Inverse transform: src = Mallat pyramid, dst = image.  Each fused step is
- * undone in reverse order (S_{-U} then T_{-P} per pair; for the integer 5/3
- * the vertical half of each step is undone before the horizontal half). */
+/* Inverse transform: src = Mallat pyramid (height x width, src_pitch), dst =
+ * image (height x width, dst_pitch); arguments, workspace and errors as for
+ * dwt2_fwd.  It inverts the factorisation of eq. (2) of Section "Background":
+ * the lifting pairs in reverse order, each step with its coefficient negated.
+ * With the fused steps of Section "Proposed Schemes" this is S_{-U} then
+ * T_{-P} per pair: the horizontal and vertical factors of a fused step act on
+ * different axes and commute, so the inverse of S_U is S_{-U} (its U U* term
+ * keeps a + sign), and likewise for T_P.  The scaling is undone first.  For
+ * the integer 5/3 the vertical half of each fused step is undone before the
+ * horizontal half, which inverts it exactly. */
 int dwt2_inv(const void* src, void* dst, int32_t height, int32_t width,
              int64_t src_pitch, int64_t dst_pitch, dwt2_dtype dtype,
              dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,
@@ -236,8 +243,9 @@ int dwt2_workspace_bytes_batched(const dwt2_image* images, int count, dwt2_dtype
  * run).  The call performs no copies or allocations and can be captured in a
  * graph.  Float storage (F32, BF16, F16); flags: DWT2_FLAG_SPLIT and a tile
  * kernel configuration (any DWT2_ALGO_TILE index of dwt2_kernel_config).  No image's
- * src and dst may overlap each other or the workspace; distinct images must
- * not share a dst.  The sum over the images of one level's tiles must stay
+ * src or dst may overlap the workspace, and no image's dst may overlap the dst
+ * or the src of any image (sources may overlap one another): every such batch
+ * is rejected with DWT2_E_ALIAS.  The sum over the images of one level's tiles must stay
  * below 2^31 - 2^16 (else DWT2_E_SHAPE).  Results equal dwt2_fwd on each image
  * (bit-identical for the same configuration). */
 int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_images, int count,

@@ -199,8 +199,8 @@ def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=
         out = torch.empty_like(x2)
     else:
         _check(out)
-        if out.shape != x.shape or out.dtype != x.dtype:
-            raise ValueError("out must match the input's shape and dtype")
+        if out.shape != x.shape or out.dtype != x.dtype or out.device != x.device:
+            raise ValueError("out must match the input's shape, dtype and device")
         if not out.is_contiguous():
             raise ValueError("out must be contiguous")
         out = out.reshape(x2.shape)
@@ -280,7 +280,20 @@ class BatchedForward:
             if x.dtype != images[0].dtype or x.device != images[0].device:
                 raise ValueError("images must share dtype and device")
         self.images = list(images)
-        self.outs = list(outs) if outs is not None else [torch.empty_like(x) for x in images]
+        if outs is None:
+            self.outs = [torch.empty_like(x) for x in images]
+        else:
+            # every pyramid is written through its data pointer and row pitch:
+            # it must have its image's shape, dtype and device, and be contiguous
+            self.outs = list(outs)
+            if len(self.outs) != len(self.images):
+                raise ValueError(f"{len(self.outs)} outputs for {len(self.images)} images")
+            for k, (x, y) in enumerate(zip(self.images, self.outs)):
+                _check(y)
+                if y.shape != x.shape or y.dtype != x.dtype or y.device != x.device:
+                    raise ValueError(f"outs[{k}] must match image {k} in shape, dtype and device")
+                if not y.is_contiguous():
+                    raise ValueError(f"outs[{k}] must be contiguous")
         self.levels = levels
         self.dtype = dtype_code(images[0])
         if config is None:

@@ -6,7 +6,10 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "dwt2.h"
 #include "dwt2_batch_plan.h"
@@ -99,6 +102,30 @@ size_t span_bytes(int32_t h, int32_t w, int64_t pitch, size_t es) {
 // Bytes from the first to the last element of `planes` planes.
 size_t planes_span_bytes(int32_t planes, int64_t plane_stride, int32_t h, int32_t w, int64_t pitch, size_t es) {
     return (size_t)(planes - 1) * (size_t)plane_stride * es + span_bytes(h, w, pitch, es);
+}
+
+// Every tile of a batched call runs in the same launch as the tiles of the
+// other images, so no image's destination may overlap another image's
+// destination or any image's source (sources may share memory: they are only
+// read).  The destination spans are sorted by start; once they are known to
+// be disjoint they are also sorted by end, so the only destination that can
+// overlap a source [a, b) is the last one starting before b.
+bool batch_spans_alias(const dwt2_image* imgs, int count, size_t es) {
+    std::vector<std::pair<uintptr_t, uintptr_t>> dst((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        const uintptr_t a = (uintptr_t)imgs[i].dst;
+        dst[(size_t)i] = {a, a + span_bytes(imgs[i].height, imgs[i].width, imgs[i].dst_pitch, es)};
+    }
+    std::sort(dst.begin(), dst.end());
+    for (size_t i = 1; i < dst.size(); ++i)
+        if (dst[i].first < dst[i - 1].second) return true;
+    for (int i = 0; i < count; ++i) {
+        const uintptr_t a = (uintptr_t)imgs[i].src;
+        const uintptr_t b = a + span_bytes(imgs[i].height, imgs[i].width, imgs[i].src_pitch, es);
+        auto it = std::lower_bound(dst.begin(), dst.end(), std::make_pair(b, (uintptr_t)0));
+        if (it != dst.begin() && std::prev(it)->second > a) return true;
+    }
+    return false;
 }
 
 // Kernel configuration selected by the flags (0 in the field = default).
@@ -446,6 +473,7 @@ int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_ima
             return DWT2_E_ALIAS;
         for (int l = 0; l < levels; ++l) tiles[l] += dwt2::level_tile_count(im.height, im.width, l, core_x, core);
     }
+    if (batch_spans_alias(host_images, count, es)) return DWT2_E_ALIAS;
     uint32_t tiles_per_level[32];
     for (int l = 0; l < levels; ++l) {
         if (tiles[l] > 0x7fff0000ull) return DWT2_E_SHAPE;     // grid of one launch

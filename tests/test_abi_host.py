@@ -177,6 +177,54 @@ def test_batched_argument_errors():
     assert fb(host=ctypes.cast(bad, ctypes.c_void_p), count=1) == -2
 
 
+def test_batched_rejects_overlap_across_images():
+    """All images' tiles run in the same launches: one image's dst must not
+    overlap another image's dst or src (sources may share memory)."""
+    L = d.lib()
+    img = 64 * 64 * 4                                   # bytes of one 64 x 64 FP32 image
+
+    def batch(*specs):
+        a = (d.dwt2_image * len(specs))()
+        for k, (s, t) in enumerate(specs):
+            a[k] = d.dwt2_image(s, t, 64, 64, 64, 64)
+        return a
+
+    def fb(arr):
+        hp = ctypes.cast(arr, ctypes.c_void_p)
+        n = ctypes.c_size_t(0)
+        assert L.dwt2_workspace_bytes_batched(hp, len(arr), d.DWT2_F32, 2, ctypes.byref(n)) == 0
+        return L.dwt2_fwd_batched(hp, ctypes.c_void_p(0x50000000), len(arr), d.DWT2_F32, d.DWT2_CDF97, 2, 0, 0,
+                                  ctypes.c_void_p(FAKE_WS), n.value, None)
+    S, T = FAKE_SRC, FAKE_DST
+    # two images writing overlapping destinations (last element of one, first of the next)
+    assert fb(batch((S, T), (S + img, T + img - 4))) == -9
+    # the same destination twice
+    assert fb(batch((S, T), (S + img, T))) == -9
+    # one image's destination inside another image's source, either order
+    assert fb(batch((S, T), (S + img, S + 8))) == -9
+    assert fb(batch((S + img, S + 8), (S, T))) == -9
+    # destinations far apart, an unordered list, and three overlapping
+    # destinations among five images
+    far = [(S + k * img, T + (4 - k) * 2 * img) for k in range(5)]
+    far[3] = (far[3][0], far[1][1] + img - 4)
+    assert fb(batch(*far)) == -9
+
+    # batches that pass the overlap check: they then fail the workspace size
+    # check that follows it (these fake pointers must never reach a launch)
+    def fb_small_ws(arr):
+        hp = ctypes.cast(arr, ctypes.c_void_p)
+        n = ctypes.c_size_t(0)
+        assert L.dwt2_workspace_bytes_batched(hp, len(arr), d.DWT2_F32, 2, ctypes.byref(n)) == 0
+        return L.dwt2_fwd_batched(hp, ctypes.c_void_p(0x50000000), len(arr), d.DWT2_F32, d.DWT2_CDF97, 2, 0, 0,
+                                  ctypes.c_void_p(FAKE_WS), n.value - 1, None)
+    far = [(S + k * img, T + (4 - k) * 2 * img) for k in range(5)]
+    assert fb_small_ws(batch(*far)) == -8
+    # sources may overlap one another: they are only read
+    assert fb_small_ws(batch((S, T), (S, T + img))) == -8
+    # adjacent destinations, touching but not overlapping
+    assert fb_small_ws(batch((S, T), (S + img, T + img))) == -8
+
+
 def test_kernel_configs_listed():
     for i in range(d.DWT2_NUM_KERNEL_CONFIGS):
         st, algo, waves, rows, cc, cr = d.dwt2_kernel_config(i)
