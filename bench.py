@@ -361,6 +361,29 @@ def main():
              lambda i, c: d.inv(ys[i % pairs], "cdf97", 1, out=xs[i % pairs], config=c, factored=True), 1, 4)
         form("cdf97 fwd f32 5 levels factored (4 barriers)",
              lambda i, c: d.fwd(xs[i % pairs], "cdf97", 5, out=ys[i % pairs], config=c, factored=True), 5, 4)
+        # the LDS-plane kernel (the paper's on-chip-memory design: tile and
+        # halo as the four polyphase planes in LDS, one barrier per step):
+        # the three schemes of Section "Proposed Schemes" side by side --
+        # polyconvolution (one step per lifting pair: 2 barriers), fused
+        # lifting (4) and separable lifting (8) -- and DD 13/7 (Section
+        # "Evaluation"), which only this kernel runs
+        lds_cfg = next(c for c in range(d.DWT2_NUM_KERNEL_CONFIGS)
+                       if d.dwt2_kernel_config(c)[1] == d.DWT2_ALGO_LDS)
+        for sch, kw in (("polyconvolution (2 barriers)", {"polyconv": True}), ("fused (4 barriers)", {}),
+                        ("separable (8 barriers)", {"separable": True})):
+            form(f"cdf97 fwd f32 1 level, LDS-plane kernel, {sch}",
+                 lambda i, c, kw=kw: d.fwd(xs[i % pairs], "cdf97", 1, out=ys[i % pairs], config=lds_cfg, **kw), 1, 4)
+            form(f"cdf97 inv f32 1 level, LDS-plane kernel, {sch}",
+                 lambda i, c, kw=kw: d.inv(ys[i % pairs], "cdf97", 1, out=xs[i % pairs], config=lds_cfg, **kw), 1, 4)
+        form("cdf97 fwd f32 5 levels, LDS-plane kernel, polyconvolution (2 barriers)",
+             lambda i, c: d.fwd(xs[i % pairs], "cdf97", 5, out=ys[i % pairs], config=lds_cfg, polyconv=True), 5, 4)
+        for sch, kw in (("fused (2 barriers)", {}), ("separable (4 barriers)", {"separable": True})):
+            form(f"dd137 fwd f32 1 level, LDS-plane kernel, {sch}",
+                 lambda i, c, kw=kw: d.fwd(xs[i % pairs], "dd137", 1, out=ys[i % pairs], config=lds_cfg, **kw), 1, 4)
+            form(f"dd137 inv f32 1 level, LDS-plane kernel, {sch}",
+                 lambda i, c, kw=kw: d.inv(ys[i % pairs], "dd137", 1, out=xs[i % pairs], config=lds_cfg, **kw), 1, 4)
+        form("dd137 fwd f32 5 levels, LDS-plane kernel, fused (2 barriers)",
+             lambda i, c: d.fwd(xs[i % pairs], "dd137", 5, out=ys[i % pairs], config=lds_cfg), 5, 4)
         del ws5
         for tdt, nm in [(torch.bfloat16, "bf16"), (torch.float16, "f16")]:
             xb = [t.to(tdt) for t in xs]

@@ -77,9 +77,17 @@ typedef enum {
 typedef enum {
     DWT2_CDF97 = 0,         /* CDF 9/7, float storage (F32, BF16, F16)          */
     DWT2_CDF53_REV = 1,     /* reversible integer CDF 5/3, I32 storage only     */
-    DWT2_CDF53 = 2          /* real-valued CDF 5/3 (the paper's 5/3, Section
+    DWT2_CDF53 = 2,         /* real-valued CDF 5/3 (the paper's 5/3, Section
                                "Evaluation"), float storage; p = -1/2,
                                u = 1/4, LL * 2, HH * 1/2 (zeta = sqrt(2))    */
+    DWT2_DD137 = 3          /* Deslauriers-Dubuc 13/7 (Section "Evaluation"),
+                               float storage: one pair of four-tap steps,
+                               odd -= (9 (e[m] + e[m+1]) - (e[m-1] + e[m+2])) / 16,
+                               even += (9 (o[m-1] + o[m]) - (o[m-2] + o[m+1])) / 32,
+                               LL * 2, HH * 1/2 (zeta = sqrt(2)); borders
+                               reflect the pixel position of each sample.
+                               Forward / inverse on DWT2_ALGO_LDS kernel
+                               configurations only (the default for it).   */
 } dwt2_wavelet;
 
 typedef enum {
@@ -119,6 +127,16 @@ typedef enum {
                                 to FP32 rounding (5/3: bit-identical).  Same
                                 restrictions as DWT2_FLAG_SEPARABLE; not
                                 together with it.                            */
+#define DWT2_FLAG_POLYCONV 8u   /* the non-separable polyconvolution scheme of
+                                Section "Proposed Schemes": each pair of lifting
+                                steps as one step N_{P,U} (V = P U + 1), every
+                                output computed from the step's inputs over a
+                                3 x 3 block neighbourhood, one barrier per pair
+                                (2 per CDF 9/7 level).  CDF 9/7 only (the paper
+                                gives it for wavelets of several pairs);
+                                forward / inverse on DWT2_ALGO_LDS kernel
+                                configurations (the default with this flag).
+                                Same values up to FP32 rounding.             */
 /* Kernel configuration: bits 8..15 hold 1 + the index of a configuration
  * listed by dwt2_kernel_config(); 0 selects the library default.  Every
  * configuration computes the same values (bit-identical for the same other
@@ -126,13 +144,21 @@ typedef enum {
 #define DWT2_FLAG_KERNEL_SHIFT 8
 #define DWT2_FLAG_KERNEL_MASK 0xff00u
 #define DWT2_FLAG_KERNEL(i) (((unsigned)(i) + 1u) << DWT2_FLAG_KERNEL_SHIFT)
-#define DWT2_NUM_KERNEL_CONFIGS 8
+#define DWT2_NUM_KERNEL_CONFIGS 10
 
 /* Kernel algorithms (dwt2_kernel_config). */
 #define DWT2_ALGO_TILE 0     /* work-group tile in VGPRs, waves stacked
                                 vertically, one LDS barrier per fused step */
 #define DWT2_ALGO_STREAM 1   /* each wave64 walks down a column strip with a
                                 register window; no LDS, no barrier */
+#define DWT2_ALGO_LDS 2      /* the tile and its halo as the four polyphase
+                                planes in LDS, one 2-D stencil and one barrier
+                                per step (the paper's on-chip-memory design);
+                                runs the fused, separable and polyconvolution
+                                schemes of the float wavelets, forward and
+                                inverse; CDF results bit-identical to the
+                                DWT2_ALGO_TILE ones for the fused and
+                                separable schemes */
 
 /* One image of a batched call.  Pitches in elements. */
 typedef struct {

@@ -23,23 +23,25 @@ LIB_PATH = os.path.join(HERE, "libdwt2.so")
 # enums of include/dwt2.h
 DWT2_OK = 0
 DWT2_E_HIP = -10
-DWT2_CDF97, DWT2_CDF53_REV, DWT2_CDF53 = 0, 1, 2
+DWT2_CDF97, DWT2_CDF53_REV, DWT2_CDF53, DWT2_DD137 = 0, 1, 2, 3
 DWT2_F32, DWT2_BF16, DWT2_F16, DWT2_I32 = 0, 1, 2, 3
 DWT2_SYMMETRIC_WHOLE = 0
 DWT2_FLAG_SPLIT = 1
 DWT2_FLAG_SEPARABLE = 2
 DWT2_FLAG_FACTORED = 4
+DWT2_FLAG_POLYCONV = 8
 DWT2_FLAG_KERNEL_SHIFT = 8
-DWT2_NUM_KERNEL_CONFIGS = 8
-DWT2_ALGO_TILE, DWT2_ALGO_STREAM = 0, 1
+DWT2_NUM_KERNEL_CONFIGS = 10
+DWT2_ALGO_TILE, DWT2_ALGO_STREAM, DWT2_ALGO_LDS = 0, 1, 2
 
 
 def DWT2_FLAG_KERNEL(i: int) -> int:
     return (i + 1) << DWT2_FLAG_KERNEL_SHIFT
 
 
-# "cdf53": the reversible integer CDF 5/3; "cdf53f": the real-valued one
-WAVELETS = {"cdf97": DWT2_CDF97, "cdf53": DWT2_CDF53_REV, "cdf53f": DWT2_CDF53}
+# "cdf53": the reversible integer CDF 5/3; "cdf53f": the real-valued one;
+# "dd137": Deslauriers-Dubuc 13/7
+WAVELETS = {"cdf97": DWT2_CDF97, "cdf53": DWT2_CDF53_REV, "cdf53f": DWT2_CDF53, "dd137": DWT2_DD137}
 
 # every function the header declares, with its ctypes signature
 _c_int, _c_i32, _c_i64, _c_u, _c_sz, _c_p = (ctypes.c_int, ctypes.c_int32, ctypes.c_int64,
@@ -191,7 +193,24 @@ def tuned_config(direction: str, wavelet: str, dtype: int, h: int, w: int, level
     return _tuned[k]
 
 
-def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=False, factored=False):
+def config_supports(index: int, direction: str, wavelet: str, scheme: str = "fused") -> bool:
+    """Whether kernel configuration `index` runs this case (the library
+    rejects the others with DWT2_E_FLAGS): the LDS-plane configurations run
+    the float wavelets forward and inverse with the fused, separable and
+    polyconvolution schemes, and are the only ones that run DD 13/7 and the
+    polyconvolution; the streaming ones run the fused and split schemes."""
+    algo = dwt2_kernel_config(index)[1]
+    if algo == DWT2_ALGO_LDS:
+        return direction in ("fwd", "inv") and wavelet != "cdf53" and scheme in ("fused", "separable", "polyconv")
+    if wavelet == "dd137" or scheme == "polyconv":
+        return False
+    if algo == DWT2_ALGO_STREAM:
+        return scheme in ("fused", "split")
+    return True
+
+
+def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=False, factored=False,
+               polyconv=False):
     torch = _torch()
     _check(x)
     x2 = x.reshape(-1, *x.shape[-2:]) if x.is_contiguous() else x.contiguous().reshape(-1, *x.shape[-2:])
@@ -209,11 +228,13 @@ def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=
     dt = dtype_code(x2)
     stream = _stream_ptr(x2)
     flags = ((DWT2_FLAG_SPLIT if split else 0) | (DWT2_FLAG_SEPARABLE if separable else 0)
-             | (DWT2_FLAG_FACTORED if factored else 0))
+             | (DWT2_FLAG_FACTORED if factored else 0) | (DWT2_FLAG_POLYCONV if polyconv else 0))
     if config is None:
         config = tuned_config(_DIRECTIONS[name], wavelet, dt, H, W, levels)
-        if (separable or factored) and config is not None and dwt2_kernel_config(config)[1] != DWT2_ALGO_TILE:
-            config = None                 # these schemes run on tile configurations
+        scheme = ("split" if split else "separable" if separable else "factored" if factored
+                  else "polyconv" if polyconv else "fused")
+        if config is not None and not config_supports(config, _DIRECTIONS[name], wavelet, scheme):
+            config = None                 # the library's default for this case
     if config is not None:
         flags |= DWT2_FLAG_KERNEL(config)
     # one call for all planes (at most 2^31 - 1 per call)
@@ -232,23 +253,26 @@ def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=
 
 
 def fwd(x, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None,
-        separable: bool = False, factored: bool = False):
+        separable: bool = False, factored: bool = False, polyconv: bool = False):
     """Forward transform of every [H, W] plane of x into a Mallat pyramid
     (all planes in one call: one launch per level).  `config` selects a
     kernel configuration index (None: tuned or library default).  At most
     one of `split` (the P0/P1 operation-count reduction), `separable` (the
-    separable comparison scheme, twice the barriers) and `factored` (each
-    fused step evaluated as its two 1-D factors, one barrier per step); all
-    compute the same values up to FP32 rounding."""
+    separable comparison scheme, twice the barriers), `factored` (each
+    fused step evaluated as its two 1-D factors, one barrier per step) and
+    `polyconv` (one polyconvolution step N_{P,U} per lifting pair, CDF 9/7,
+    LDS-plane kernel); all compute the same values up to FP32 rounding.
+    Wavelets: "cdf97", "cdf53" (reversible integer), "cdf53f" (real CDF
+    5/3), "dd137" (Deslauriers-Dubuc 13/7, LDS-plane kernel)."""
     return _transform(lib().dwt2_fwd_planes, "dwt2_fwd", x, wavelet, levels, split, out, config, separable,
-                      factored)
+                      factored, polyconv)
 
 
 def inv(c, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None,
-        separable: bool = False, factored: bool = False):
+        separable: bool = False, factored: bool = False, polyconv: bool = False):
     """Inverse transform of every [H, W] Mallat pyramid of c."""
     return _transform(lib().dwt2_inv_planes, "dwt2_inv", c, wavelet, levels, split, out, config, separable,
-                      factored)
+                      factored, polyconv)
 
 
 def adj(g, levels: int = 1, out=None, config=None):

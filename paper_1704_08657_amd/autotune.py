@@ -81,7 +81,7 @@ def tune_case(direction: str, wavelet: str, dtype: str, h: int, w: int, levels: 
     import torch
     import paper_1704_08657_amd as d
     if configs is None:
-        configs = range(d.DWT2_NUM_KERNEL_CONFIGS)
+        configs = [c for c in range(d.DWT2_NUM_KERNEL_CONFIGS) if d.config_supports(c, direction, wavelet)]
     times = {c: _time(torch, lambda i, c=c: run(c, i), steps=steps, warm=warm) for c in configs}
     best = min(times, key=times.get)
     cache = load_cache()
@@ -142,6 +142,8 @@ def tune(sizes=(256, 1024, 4096, 8192), levels=(1, 5), quick=False, out=CACHE_PA
               "adj": lambda x, y, c: d.adj(x, lv, out=y, config=c)}[direction]
         best, best_ms = None, float("inf")
         for c in range(nconf):
+            if not d.config_supports(c, direction, wav):
+                continue
             ms = _time(torch, lambda i: fn(xs[i % nb], ys[i % nb], c), steps=8 if quick else 30)
             if ms < best_ms:
                 best, best_ms = c, ms

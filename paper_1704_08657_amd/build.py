@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdwt2.so")
 ARCH = os.environ.get("DWT2_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["dwt2_fwd.hip", "dwt2_inv.hip", "dwt2_adj.hip", "dwt2_batched.hip", "dwt2_dispatch.cpp", "dwt2_api.cpp"]
+SOURCES = ["dwt2_fwd.hip", "dwt2_inv.hip", "dwt2_adj.hip", "dwt2_batched.hip", "dwt2_lds.hip", "dwt2_dispatch.cpp",
+           "dwt2_api.cpp"]
 
 # Packed FP32 instructions are disabled for every HIP translation unit.
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

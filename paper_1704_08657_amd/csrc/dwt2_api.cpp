@@ -128,16 +128,20 @@ bool batch_spans_alias(const dwt2_image* imgs, int count, size_t es) {
     return false;
 }
 
-// Kernel configuration selected by the flags (0 in the field = default).
-int config_of(unsigned flags) {
+// Kernel configuration selected by the flags (0 in the field = the default:
+// the LDS-plane kernel for DD 13/7 and the polyconvolution, which only it
+// runs; the register tile kernel otherwise).
+int config_of(unsigned flags, int wavelet) {
     const unsigned t = (flags & DWT2_FLAG_KERNEL_MASK) >> DWT2_FLAG_KERNEL_SHIFT;
-    return t == 0 ? dwt2::kDefaultConfig : (int)t - 1;
+    if (t != 0) return (int)t - 1;
+    return (wavelet == DWT2_DD137 || (flags & DWT2_FLAG_POLYCONV)) ? dwt2::kDefaultLdsConfig : dwt2::kDefaultConfig;
 }
 
 dwt2::Scheme scheme_of(unsigned flags) {
     if (flags & DWT2_FLAG_SPLIT) return dwt2::kSchemeSplit;
     if (flags & DWT2_FLAG_SEPARABLE) return dwt2::kSchemeSeparable;
     if (flags & DWT2_FLAG_FACTORED) return dwt2::kSchemeFactored;
+    if (flags & DWT2_FLAG_POLYCONV) return dwt2::kSchemePolyconv;
     return dwt2::kSchemeFused;
 }
 
@@ -146,24 +150,36 @@ int validate(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dp
              const void* ws, size_t ws_bytes, bool adjoint) {
     if (!src || !dst) return DWT2_E_NULL;
     if (planes < 1) return DWT2_E_COUNT;
-    if (wavelet != DWT2_CDF97 && wavelet != DWT2_CDF53_REV && wavelet != DWT2_CDF53) return DWT2_E_WAVELET;
+    if (wavelet != DWT2_CDF97 && wavelet != DWT2_CDF53_REV && wavelet != DWT2_CDF53 && wavelet != DWT2_DD137)
+        return DWT2_E_WAVELET;
     if (dtype != DWT2_F32 && dtype != DWT2_BF16 && dtype != DWT2_F16 && dtype != DWT2_I32)
         return DWT2_E_DTYPE;
     if ((wavelet == DWT2_CDF53_REV) != (dtype == DWT2_I32)) return DWT2_E_DTYPE;
     if (boundary != DWT2_SYMMETRIC_WHOLE) return DWT2_E_BOUNDARY;
-    if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED | DWT2_FLAG_KERNEL_MASK))
+    if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED | DWT2_FLAG_POLYCONV |
+                  DWT2_FLAG_KERNEL_MASK))
         return DWT2_E_FLAGS;
     if (((flags & DWT2_FLAG_KERNEL_MASK) >> DWT2_FLAG_KERNEL_SHIFT) > (unsigned)dwt2::kNumConfigs)
         return DWT2_E_FLAGS;
+    if (adjoint && wavelet != DWT2_CDF97) return DWT2_E_WAVELET;
     if ((flags & DWT2_FLAG_SPLIT) && (wavelet == DWT2_CDF53_REV || adjoint)) return DWT2_E_FLAGS;
     // at most one scheme flag; the separable and factored schemes: forward /
-    // inverse on tile configurations
-    const unsigned schemes = flags & (DWT2_FLAG_SPLIT | DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED);
+    // inverse on tile configurations (the separable one also on LDS-plane
+    // configurations); the polyconvolution: CDF 9/7 forward / inverse on
+    // LDS-plane configurations
+    const unsigned schemes = flags & (DWT2_FLAG_SPLIT | DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED | DWT2_FLAG_POLYCONV);
     if (schemes & (schemes - 1)) return DWT2_E_FLAGS;
-    if ((flags & (DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED)) &&
-        (adjoint || dwt2::kConfigs[config_of(flags)].algo != dwt2::kAlgoTile))
+    const int algo = dwt2::kConfigs[config_of(flags, wavelet)].algo;
+    if ((flags & (DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED)) && (adjoint || algo == dwt2::kAlgoStream))
         return DWT2_E_FLAGS;
-    if (adjoint && wavelet != DWT2_CDF97) return DWT2_E_WAVELET;
+    if ((flags & DWT2_FLAG_POLYCONV) && wavelet != DWT2_CDF97) return DWT2_E_FLAGS;
+    // the LDS-plane kernel: float wavelets, forward / inverse, fused,
+    // separable and polyconvolution schemes; it alone runs DD 13/7 and the
+    // polyconvolution
+    if (algo == dwt2::kAlgoLds &&
+        (adjoint || wavelet == DWT2_CDF53_REV || (flags & (DWT2_FLAG_SPLIT | DWT2_FLAG_FACTORED))))
+        return DWT2_E_FLAGS;
+    if (algo != dwt2::kAlgoLds && (wavelet == DWT2_DD137 || (flags & DWT2_FLAG_POLYCONV))) return DWT2_E_FLAGS;
     if (h < 2 || w < 2 || h > kMaxSide || w > kMaxSide) return DWT2_E_SHAPE;
     if (sp < w || dp < w) return DWT2_E_PITCH;
     // planes of one buffer must not overlap
@@ -191,14 +207,15 @@ int report(hipError_t e) {
 
 dwt2::Dtype to_dtype(int d) { return (dwt2::Dtype)d; }
 dwt2::Wavelet to_wav(int w) {
-    return w == DWT2_CDF97 ? dwt2::kCdf97 : w == DWT2_CDF53 ? dwt2::kCdf53Real : dwt2::kCdf53;
+    return w == DWT2_CDF97 ? dwt2::kCdf97 : w == DWT2_CDF53 ? dwt2::kCdf53Real : w == DWT2_DD137 ? dwt2::kDd137
+                                                                                                  : dwt2::kCdf53;
 }
 
 // Work-group grid of one level for kernel configuration `cfg`.
 void plan_grid(int cfg, dwt2::LevelParams* lp) {
     const dwt2::KernelConfig c = dwt2::kConfigs[cfg];
     const int32_t nEr = (lp->h + 1) / 2, nEc = (lp->w + 1) / 2;
-    if (c.algo == dwt2::kAlgoTile) {
+    if (c.algo != dwt2::kAlgoStream) {
         const int cy = dwt2::core_rows(c);
         const int cx = dwt2::core_cols(c);
         lp->tiles_x = (nEc + cx - 1) / cx;
@@ -226,7 +243,7 @@ int launch_planes(dwt2::Direction dir, int wavelet, int dtype, unsigned flags, d
             q.out_ll = lp.out_ll ? (char*)lp.out_ll + (size_t)p0 * (size_t)lp.out_ll_ps * es : nullptr;
         }
         const int rc = report(dwt2::launch_level(dir, to_wav(wavelet), to_dtype(dtype), scheme_of(flags),
-                                                 config_of(flags), q, n, s));
+                                                 config_of(flags, wavelet), q, n, s));
         if (rc) return rc;
     }
     return DWT2_OK;
@@ -265,9 +282,9 @@ int run_forward(const void* src, void* dst, int32_t planes, int64_t sps, int64_t
         lp.out_ll = last ? dst : (void*)bufs[l % 2];
         lp.out_ll_pitch = last ? dp : ws_pitch((lp.w + 1) / 2);
         lp.out_ll_ps = last ? dps : buf_ps[l % 2];
-        plan_grid(config_of(flags), &lp);
+        plan_grid(config_of(flags, wavelet), &lp);
         const int32_t nEc = (lp.w + 1) / 2;
-        const int sv = dwt2::subband_vec(dwt2::kConfigs[config_of(flags)]);
+        const int sv = dwt2::subband_vec(dwt2::kConfigs[config_of(flags, wavelet)]);
         lp.vec = aligned(lp.in, 4 * es) && lp.in_pitch % 4 == 0 && stride_ok(planes, lp.in_ps, 4) &&
                  aligned(lp.out, sv * es) && lp.out_pitch % sv == 0 && stride_ok(planes, lp.out_ps, sv) &&
                  nEc % sv == 0 && aligned(lp.out_ll, sv * es) && lp.out_ll_pitch % sv == 0 &&
@@ -313,9 +330,9 @@ int run_backward(dwt2::Direction dir, const void* src, void* dst, int32_t planes
         lp.out = l == 0 ? dst : (void*)bufs[(l - 1) % 2];
         lp.out_pitch = l == 0 ? dp : ws_pitch(lp.w);
         lp.out_ps = l == 0 ? dps : buf_ps[(l - 1) % 2];
-        plan_grid(config_of(flags), &lp);
+        plan_grid(config_of(flags, wavelet), &lp);
         const int32_t nEc = (lp.w + 1) / 2;
-        const int sv = dwt2::subband_vec(dwt2::kConfigs[config_of(flags)]);
+        const int sv = dwt2::subband_vec(dwt2::kConfigs[config_of(flags, wavelet)]);
         lp.vec = aligned(lp.in, sv * es) && lp.in_pitch % sv == 0 && stride_ok(planes, lp.in_ps, sv) &&
                  nEc % sv == 0 && aligned(lp.in_ll, sv * es) && lp.in_ll_pitch % sv == 0 &&
                  stride_ok(planes, lp.in_ll_ps, sv) && aligned(lp.out, 4 * es) && lp.out_pitch % 4 == 0 &&
@@ -421,8 +438,8 @@ int dwt2_kernel_config(int index, int* algorithm, int* waves, int* rows, int* co
     if (algorithm) *algorithm = c.algo;
     if (waves) *waves = c.waves;
     if (rows) *rows = c.rows;
-    if (core_cols) *core_cols = c.algo == dwt2::kAlgoTile ? dwt2::core_cols(c) : dwt2::kStreamCoreBX;
-    if (core_rows) *core_rows = c.algo == dwt2::kAlgoTile ? dwt2::core_rows(c) : c.seg;
+    if (core_cols) *core_cols = c.algo != dwt2::kAlgoStream ? dwt2::core_cols(c) : dwt2::kStreamCoreBX;
+    if (core_rows) *core_rows = c.algo != dwt2::kAlgoStream ? dwt2::core_rows(c) : c.seg;
     return DWT2_OK;
 }
 
@@ -456,7 +473,7 @@ int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_ima
     if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_KERNEL_MASK)) return DWT2_E_FLAGS;
     if (((flags & DWT2_FLAG_KERNEL_MASK) >> DWT2_FLAG_KERNEL_SHIFT) > (unsigned)dwt2::kNumConfigs)
         return DWT2_E_FLAGS;
-    const int cfg = config_of(flags);
+    const int cfg = config_of(flags, wavelet);
     if (!dwt2::batched_config_supported(cfg)) return DWT2_E_FLAGS;
     const size_t es = elem_size(dtype);
     const int core = dwt2::core_rows(dwt2::kConfigs[cfg]);

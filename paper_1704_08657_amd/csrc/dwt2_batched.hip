@@ -167,7 +167,7 @@ hipError_t launch_batched_shape(const dwt2_image* dev_imgs, int count, int level
 template <typename T, bool SPLIT>
 hipError_t launch_batched_cfg(int cfg, const dwt2_image* d, int count, int levels, void* ws, const uint32_t* tpl,
                               hipStream_t s) {
-    static_assert(kNumConfigs == 8, "dispatch table below lists every kernel configuration");
+    static_assert(kNumConfigs == 10, "dispatch table below lists every kernel configuration");
 #define DWT2_BCFG(i)                                                                               \
     case i:                                                                                        \
         if constexpr (kConfigs[i].algo == kAlgoTile)                                               \
@@ -177,6 +177,7 @@ hipError_t launch_batched_cfg(int cfg, const dwt2_image* d, int count, int level
             return hipErrorInvalidValue;
     switch (cfg) {
         DWT2_BCFG(0) DWT2_BCFG(1) DWT2_BCFG(2) DWT2_BCFG(3) DWT2_BCFG(4) DWT2_BCFG(5) DWT2_BCFG(6) DWT2_BCFG(7)
+        DWT2_BCFG(8) DWT2_BCFG(9)
     }
 #undef DWT2_BCFG
     return hipErrorInvalidValue;

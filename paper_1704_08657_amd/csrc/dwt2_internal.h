@@ -11,14 +11,17 @@ namespace dwt2 {
 
 enum Direction : int { kForward = 0, kInverse = 1, kAdjoint = 2 };
 // kCdf53: the reversible integer CDF 5/3; kCdf53Real: the real-valued one
-enum Wavelet : int { kCdf97 = 0, kCdf53 = 1, kCdf53Real = 2 };
+enum Wavelet : int { kCdf97 = 0, kCdf53 = 1, kCdf53Real = 2, kDd137 = 3 };
 enum Dtype : int { kF32 = 0, kBF16 = 1, kF16 = 2, kI32 = 3 };
 // Lifting scheme of a level: the fused non-separable steps, the fused steps
 // with the P0/P1 split, the separable steps (the comparison scheme: every
 // fused step replaced by its horizontal and its vertical step, a barrier
 // each), or the fused steps evaluated as those two factors in registers (one
 // barrier per fused step: the horizontal factor never leaves the wave).
-enum Scheme : int { kSchemeFused = 0, kSchemeSplit = 1, kSchemeSeparable = 2, kSchemeFactored = 3 };
+// The LDS-plane kernel (kAlgoLds) also runs the non-separable
+// polyconvolution: one step N_{P,U} per lifting pair.
+enum Scheme : int { kSchemeFused = 0, kSchemeSplit = 1, kSchemeSeparable = 2, kSchemeFactored = 3,
+                    kSchemePolyconv = 4 };
 
 // Geometry shared by host planning and the kernels, in blocks of 2x2 pixels.
 // A tile (kAlgoTile) has 64 * bpl output columns (bpl blocks per lane) and
@@ -37,28 +40,36 @@ constexpr int kStreamCoreBX = 2 * kLanes - 2 * kHalo;     // stream kernel: 124 
 //  kAlgoStream: every wave64 walks down its own column strip of 128 blocks,
 //               `rows` block rows of loads in flight ahead of the computation;
 //               `waves` strips per work-group; `seg` block rows per segment.
-enum Algo : int { kAlgoTile = 0, kAlgoStream = 1 };
+//  kAlgoLds:    the tile with its halo held as the four polyphase planes
+//               in LDS (double-buffered), every step a 2-D stencil over them
+//               with one barrier; `cx` x `cy` output blocks per work-group of
+//               `waves` wave64s.  Runs any step program: fused, separable
+//               and polyconvolution schemes, two-tap and four-tap filters.
+enum Algo : int { kAlgoTile = 0, kAlgoStream = 1, kAlgoLds = 2 };
 struct KernelConfig {
     int algo;
     int waves;
     int rows;
     int seg;
     int bpl;    // kAlgoTile: block columns per lane (2 or 4)
+    int cx, cy; // kAlgoLds: output blocks of one work-group tile
 };
 constexpr KernelConfig kConfigs[] = {
-    {kAlgoTile, 4, 4, 0, 2},    {kAlgoTile, 8, 4, 0, 2},    {kAlgoTile, 4, 4, 0, 4},
-    {kAlgoTile, 4, 6, 0, 2},    {kAlgoTile, 8, 2, 0, 4},    {kAlgoStream, 4, 8, 64, 2},
-    {kAlgoStream, 1, 8, 64, 2}, {kAlgoStream, 4, 8, 32, 2}};
-constexpr int kNumConfigs = 8;
+    {kAlgoTile, 4, 4, 0, 2, 0, 0},    {kAlgoTile, 8, 4, 0, 2, 0, 0},    {kAlgoTile, 4, 4, 0, 4, 0, 0},
+    {kAlgoTile, 4, 6, 0, 2, 0, 0},    {kAlgoTile, 8, 2, 0, 4, 0, 0},    {kAlgoStream, 4, 8, 64, 2, 0, 0},
+    {kAlgoStream, 1, 8, 64, 2, 0, 0}, {kAlgoStream, 4, 8, 32, 2, 0, 0}, {kAlgoLds, 4, 0, 0, 0, 64, 16},
+    {kAlgoLds, 4, 0, 0, 0, 32, 32}};
+constexpr int kNumConfigs = 10;
 constexpr int kDefaultConfig = 0;
+constexpr int kDefaultLdsConfig = 8;
 // Tile kernels deal work over the 8 XCDs in chunks of kRemapRows tile rows
 // (a level) or kBatchChunk tiles (a batched launch); the grid is a multiple
 // of 8 chunks.
 constexpr int kRemapRows = 2;
 constexpr int kBatchChunk = 64;
-// output block rows / columns of one tile (kAlgoTile)
-constexpr int core_rows(KernelConfig c) { return c.waves * c.rows - 2 * kHalo; }
-constexpr int core_cols(KernelConfig c) { return kLanes * c.bpl; }
+// output block rows / columns of one tile (kAlgoTile, kAlgoLds)
+constexpr int core_rows(KernelConfig c) { return c.algo == kAlgoLds ? c.cy : c.waves * c.rows - 2 * kHalo; }
+constexpr int core_cols(KernelConfig c) { return c.algo == kAlgoLds ? c.cx : kLanes * c.bpl; }
 // samples per vector access of a subband row (alignment the `vec` path needs)
 constexpr int subband_vec(KernelConfig c) { return c.algo == kAlgoTile ? c.bpl : 2; }
 
@@ -100,6 +111,10 @@ constexpr int kMaxGridPlanes = 65535;
 // kSchemeSeparable and kSchemeFactored run on the tile configurations only.
 hipError_t launch_level(Direction dir, Wavelet wav, Dtype dt, Scheme scheme, int cfg,
                         const LevelParams& p, int planes, hipStream_t stream);
+// The LDS-plane kernel (kConfigs[cfg].algo == kAlgoLds): forward and inverse
+// of the float wavelets, fused / separable / polyconvolution schemes.
+hipError_t launch_lds(Direction dir, Wavelet wav, Dtype dt, Scheme scheme, int cfg, const LevelParams& p,
+                      int planes, hipStream_t stream);
 
 // Batched forward CDF 9/7 (planner + one launch per level) for the tile
 // kernel configurations (batched_config_supported).

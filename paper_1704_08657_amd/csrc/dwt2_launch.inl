@@ -55,20 +55,23 @@ hipError_t launch_stream(const LevelParams& p, int planes, hipStream_t s) {
 
 template <int DIR, int WAV, typename T, int SCH>
 hipError_t launch(int cfg, const LevelParams& p, int planes, hipStream_t s) {
-    static_assert(kNumConfigs == 8, "dispatch table below lists every kernel configuration");
-    // the streaming kernels implement the fused steps (with or without the split)
+    static_assert(kNumConfigs == 10, "dispatch table below lists every kernel configuration");
+    // the streaming kernels implement the fused steps (with or without the
+    // split); the LDS-plane configurations are dispatched by launch_level
 #define DWT2_CFG(i)                                                                              \
     case i:                                                                                      \
         if constexpr (kConfigs[i].algo == kAlgoTile)                                             \
             return launch_shape<DIR, WAV, T, SCH, kConfigs[i].waves, kConfigs[i].rows,           \
                                 kConfigs[i].bpl>(p, planes, s);                                  \
-        else if constexpr (SCH == kSchemeFused || SCH == kSchemeSplit)                           \
+        else if constexpr (kConfigs[i].algo == kAlgoStream &&                                    \
+                           (SCH == kSchemeFused || SCH == kSchemeSplit))                         \
             return launch_stream<DIR, WAV, T, SCH == kSchemeSplit, kConfigs[i].waves,            \
                                  kConfigs[i].rows>(p, planes, s);                                \
         else                                                                                     \
             return hipErrorInvalidValue;
     switch (cfg) {
         DWT2_CFG(0) DWT2_CFG(1) DWT2_CFG(2) DWT2_CFG(3) DWT2_CFG(4) DWT2_CFG(5) DWT2_CFG(6) DWT2_CFG(7)
+        DWT2_CFG(8) DWT2_CFG(9)
     }
 #undef DWT2_CFG
     return hipErrorInvalidValue;
@@ -87,8 +90,8 @@ hipError_t launch_float(Scheme sch, int cfg, const LevelParams& p, int planes, h
             case kSchemeSplit: return launch<DIR, WAV, T, kSchemeSplit>(cfg, p, planes, s);
             case kSchemeSeparable: return launch<DIR, WAV, T, kSchemeSeparable>(cfg, p, planes, s);
             case kSchemeFactored: return launch<DIR, WAV, T, kSchemeFactored>(cfg, p, planes, s);
+            default: return hipErrorInvalidValue;
         }
-        return hipErrorInvalidValue;
     }
 }
 

@@ -228,7 +228,7 @@ def test_batched_rejects_overlap_across_images():
 def test_kernel_configs_listed():
     for i in range(d.DWT2_NUM_KERNEL_CONFIGS):
         st, algo, waves, rows, cc, cr = d.dwt2_kernel_config(i)
-        assert st == 0 and algo in (d.DWT2_ALGO_TILE, d.DWT2_ALGO_STREAM) and waves >= 1 and cr >= 1
+        assert st == 0 and algo in (d.DWT2_ALGO_TILE, d.DWT2_ALGO_STREAM, d.DWT2_ALGO_LDS) and waves >= 1 and cr >= 1
     assert d.dwt2_kernel_config(d.DWT2_NUM_KERNEL_CONFIGS)[0] == -11
 
 
@@ -256,3 +256,41 @@ def test_plane_batch_argument_errors():
     # one plane: the stride is not used
     st, n1 = d.dwt2_workspace_bytes(64, 64, 2, d.DWT2_F32)
     assert fp(planes=1, sps=0, dps=0, ws_n=n1 - 1) == -8
+
+
+def test_lds_kernel_argument_rules():
+    """DD 13/7 and the polyconvolution run on the LDS-plane configurations
+    only (the default for them); those configurations run the float
+    wavelets' forward and inverse with the fused, separable and
+    polyconvolution schemes.  Every call below fails its checks on the host
+    (fake pointers)."""
+    L = d.lib()
+    lds = [i for i in range(d.DWT2_NUM_KERNEL_CONFIGS) if d.dwt2_kernel_config(i)[1] == d.DWT2_ALGO_LDS]
+    tile = [i for i in range(d.DWT2_NUM_KERNEL_CONFIGS) if d.dwt2_kernel_config(i)[1] == d.DWT2_ALGO_TILE]
+    assert lds and tile
+
+    def c(fn, wav=d.DWT2_CDF97, dtype=d.DWT2_F32, flags=0, dst=FAKE_DST):
+        return fn(ctypes.c_void_p(FAKE_SRC), ctypes.c_void_p(dst), 64, 64, 64, 64, dtype, wav, 1, 0, flags,
+                  None, 0, None)
+    for fn in (L.dwt2_fwd, L.dwt2_inv):
+        assert c(fn, wav=d.DWT2_DD137, flags=d.DWT2_FLAG_KERNEL(tile[0])) == -11
+        assert c(fn, flags=d.DWT2_FLAG_POLYCONV | d.DWT2_FLAG_KERNEL(tile[0])) == -11
+        assert c(fn, wav=d.DWT2_CDF53, flags=d.DWT2_FLAG_POLYCONV) == -11      # one pair: no polyconvolution
+        assert c(fn, wav=d.DWT2_DD137, flags=d.DWT2_FLAG_POLYCONV) == -11
+        assert c(fn, flags=d.DWT2_FLAG_POLYCONV | d.DWT2_FLAG_SEPARABLE) == -11
+        assert c(fn, wav=d.DWT2_CDF53_REV, dtype=d.DWT2_I32, flags=d.DWT2_FLAG_KERNEL(lds[0])) == -11
+        assert c(fn, flags=d.DWT2_FLAG_SPLIT | d.DWT2_FLAG_KERNEL(lds[0])) == -11
+        assert c(fn, flags=d.DWT2_FLAG_FACTORED | d.DWT2_FLAG_KERNEL(lds[0])) == -11
+        assert c(fn, wav=d.DWT2_DD137, dtype=d.DWT2_I32) == -4
+        # valid otherwise: only the overlap check (dst inside src) stops these
+        assert c(fn, wav=d.DWT2_DD137, dst=FAKE_SRC + 8) == -9
+        assert c(fn, flags=d.DWT2_FLAG_POLYCONV, dst=FAKE_SRC + 8) == -9
+        assert c(fn, flags=d.DWT2_FLAG_SEPARABLE | d.DWT2_FLAG_KERNEL(lds[1]), dst=FAKE_SRC + 8) == -9
+    assert c(L.dwt2_adj, wav=d.DWT2_DD137) == -5
+    assert c(L.dwt2_adj, flags=d.DWT2_FLAG_KERNEL(lds[0])) == -11
+    for i in lds:
+        st, algo, waves, rows, cc, cr = d.dwt2_kernel_config(i)
+        assert (st, algo, waves) == (0, d.DWT2_ALGO_LDS, 4) and cc >= 32 and cr >= 16
+    # the binding's table of supported cases agrees
+    assert d.config_supports(lds[0], "fwd", "dd137") and not d.config_supports(tile[0], "fwd", "dd137")
+    assert d.config_supports(lds[0], "inv", "cdf97", "polyconv") and not d.config_supports(lds[0], "adj", "cdf97")

@@ -81,9 +81,9 @@ def test_every_config_and_scheme(shape):
     ref = lifting.fwd(x, WAV, lv)
     xg = gpu(x)
     for cfg in range(d.DWT2_NUM_KERNEL_CONFIGS):
-        tile = d.dwt2_kernel_config(cfg)[1] == d.DWT2_ALGO_TILE
         for kw in SCHEMES:
-            if not tile and ("separable" in kw or "factored" in kw):
+            scheme = next((k for k in ("split", "separable", "factored") if kw.get(k)), "fused")
+            if not d.config_supports(cfg, "fwd", WAV, scheme):
                 continue
             say(WAV, "config", cfg, shape, lv, kw)
             y = d.fwd(xg, WAV, lv, config=cfg, **kw)

@@ -233,6 +233,8 @@ def test_kernel_configs_bit_identical():
         ref_f = d.fwd(x, wav, lv, split=split, config=0)
         ref_i = d.inv(ref_f, wav, lv, split=split, config=0)
         for sh in range(1, d.DWT2_NUM_KERNEL_CONFIGS):
+            if not d.config_supports(sh, "fwd", wav, "split" if split else "fused"):
+                continue                  # the LDS-plane kernel runs neither the split nor the integer 5/3
             say("kernel config", sh, wav, tdt, (h, w), lv, split)
             f = d.fwd(x, wav, lv, split=split, config=sh)
             if split:
@@ -249,7 +251,8 @@ def test_kernel_configs_bit_identical():
             g = ref_f
             a0 = d.adj(g, lv, config=0)
             for sh in range(1, d.DWT2_NUM_KERNEL_CONFIGS):
-                assert torch.equal(d.adj(g, lv, config=sh), a0)
+                if d.config_supports(sh, "adj", wav):
+                    assert torch.equal(d.adj(g, lv, config=sh), a0)
 
 
 # ---- every tile configuration against the oracle ---------------------------
@@ -328,15 +331,17 @@ def test_plane_batch_equals_single_planes(shape, lv):
     xi = gpu(np.stack([workloads.pixels_u8(h, w, seed=32 + k) for k in range(n)]))
     for cfg in range(d.DWT2_NUM_KERNEL_CONFIGS):
         say("plane batch", shape, lv, cfg)
+        full = d.config_supports(cfg, "adj", "cdf97")       # adjoint and integer 5/3 too
         y = d.fwd(x, "cdf97", lv, config=cfg)
         r = d.inv(y, "cdf97", lv, config=cfg)
-        a = d.adj(y, lv, config=cfg)
-        yi = d.fwd(xi, "cdf53", lv, config=cfg)
+        a = d.adj(y, lv, config=cfg) if full else None
+        yi = d.fwd(xi, "cdf53", lv, config=cfg) if full else None
         for k in range(n):
             assert torch.equal(y[k], d.fwd(x[k], "cdf97", lv, config=cfg)), (cfg, k)
             assert torch.equal(r[k], d.inv(y[k], "cdf97", lv, config=cfg)), (cfg, k)
-            assert torch.equal(a[k], d.adj(y[k], lv, config=cfg)), (cfg, k)
-            assert torch.equal(yi[k], d.fwd(xi[k], "cdf53", lv, config=cfg)), (cfg, k)
+            if full:
+                assert torch.equal(a[k], d.adj(y[k], lv, config=cfg)), (cfg, k)
+                assert torch.equal(yi[k], d.fwd(xi[k], "cdf53", lv, config=cfg)), (cfg, k)
     assert rel_err(host(y[0]), lifting.fwd(host(x[0]), "cdf97", lv)) <= TOL97
 
 
