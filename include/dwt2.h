@@ -71,7 +71,9 @@ typedef enum {
     DWT2_E_ALIAS = -9,      /* src, dst or workspace overlap                    */
     DWT2_E_HIP = -10,       /* HIP runtime error at launch                      */
     DWT2_E_FLAGS = -11,     /* unknown flag, or flag not valid for the wavelet  */
-    DWT2_E_COUNT = -12      /* batched call: count < 1; plane batch: planes < 1 */
+    DWT2_E_COUNT = -12,     /* batched call: count < 1; plane batch: planes < 1 */
+    DWT2_E_SCRATCH = -13    /* dwt2_fwd_noalloc: the call needs more workspace
+                               than DWT2_SCRATCH_BYTES                          */
 } dwt2_status;
 
 typedef enum {
@@ -277,6 +279,25 @@ int dwt2_workspace_bytes_batched(const dwt2_image* images, int count, dwt2_dtype
 int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_images, int count,
                      dwt2_dtype dtype, dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,
                      unsigned flags, void* workspace, size_t workspace_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): dwt2_fwd with
+ * no workspace argument.  The intermediate LL bands go to a fixed device
+ * array of DWT2_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends (enough for any level count of an 8192 x 8192 FP32
+ * image); the call allocates and frees nothing.  Arguments, results and
+ * errors as dwt2_fwd (bit-identical results); a call that needs more
+ * workspace than the array (dwt2_workspace_bytes) returns DWT2_E_SCRATCH
+ * before any HIP call.  The first call on a device looks up the array's
+ * address there (current device).  All calls on one GPU share its array and
+ * nothing in it has to start at zero: calls ordered on one stream are safe,
+ * calls that can overlap in time on one GPU (other streams, other host
+ * threads) race on it. */
+#define DWT2_SCRATCH_BYTES ((size_t)96 << 20)
+int dwt2_fwd_noalloc(const void* src, void* dst, int32_t height, int32_t width,
+                     int64_t src_pitch, int64_t dst_pitch, dwt2_dtype dtype,
+                     dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,
+                     unsigned flags, void* stream);
 
 /* Text of a dwt2_status. */
 const char* dwt2_status_string(int status);

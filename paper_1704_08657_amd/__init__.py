@@ -23,6 +23,8 @@ LIB_PATH = os.path.join(HERE, "libdwt2.so")
 # enums of include/dwt2.h
 DWT2_OK = 0
 DWT2_E_HIP = -10
+DWT2_E_SCRATCH = -13
+DWT2_SCRATCH_BYTES = 96 << 20
 DWT2_CDF97, DWT2_CDF53_REV, DWT2_CDF53, DWT2_DD137 = 0, 1, 2, 3
 DWT2_F32, DWT2_BF16, DWT2_F16, DWT2_I32 = 0, 1, 2, 3
 DWT2_SYMMETRIC_WHOLE = 0
@@ -63,6 +65,8 @@ SIGNATURES = {
     "dwt2_kernel_config": (_c_int, [_c_int] + [ctypes.POINTER(_c_int)] * 5),
     "dwt2_workspace_bytes_batched": (_c_int, [_c_p, _c_int, _c_int, _c_int, ctypes.POINTER(_c_sz)]),
     "dwt2_fwd_batched": (_c_int, [_c_p, _c_p, _c_int, _c_int, _c_int, _c_int, _c_int, _c_u, _c_p, _c_sz, _c_p]),
+    "dwt2_fwd_noalloc": (_c_int, [_c_p, _c_p, _c_i32, _c_i32, _c_i64, _c_i64, _c_int, _c_int, _c_int, _c_int,
+                                  _c_u, _c_p]),
     "dwt2_status_string": (ctypes.c_char_p, [_c_int]),
     "dwt2_last_hip_error": (ctypes.c_char_p, []),
 }
@@ -117,6 +121,10 @@ def dwt2_inv(*args) -> int:
 
 def dwt2_adj(*args) -> int:
     return lib().dwt2_adj(*args)
+
+
+def dwt2_fwd_noalloc(*args) -> int:
+    return lib().dwt2_fwd_noalloc(*args)
 
 
 def dwt2_kernel_config(index: int):

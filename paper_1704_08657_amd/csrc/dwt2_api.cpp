@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -147,7 +148,7 @@ dwt2::Scheme scheme_of(unsigned flags) {
 
 int validate(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dps, int32_t h, int32_t w,
              int64_t sp, int64_t dp, int dtype, int wavelet, int levels, int boundary, unsigned flags,
-             const void* ws, size_t ws_bytes, bool adjoint) {
+             const void* ws, size_t ws_bytes, bool adjoint, bool own_ws = false) {
     if (!src || !dst) return DWT2_E_NULL;
     if (planes < 1) return DWT2_E_COUNT;
     if (wavelet != DWT2_CDF97 && wavelet != DWT2_CDF53_REV && wavelet != DWT2_CDF53 && wavelet != DWT2_DD137)
@@ -188,11 +189,12 @@ int validate(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dp
     if (levels < 1 || levels > max_levels(h, w)) return DWT2_E_LEVELS;
     size_t need = 0;
     dwt2_workspace_bytes_planes(h, w, levels, (dwt2_dtype)dtype, planes, &need);
-    if (need > 0 && (!ws || ws_bytes < need)) return DWT2_E_WORKSPACE;
+    // own_ws: the workspace is the library's scratch array (checked by the caller)
+    if (need > 0 && !own_ws && (!ws || ws_bytes < need)) return DWT2_E_WORKSPACE;
     const size_t es = elem_size(dtype);
     const size_t ns = planes_span_bytes(planes, sps, h, w, sp, es), nd = planes_span_bytes(planes, dps, h, w, dp, es);
     if (ranges_overlap(src, ns, dst, nd)) return DWT2_E_ALIAS;
-    if (need > 0 && (ranges_overlap(ws, need, src, ns) || ranges_overlap(ws, need, dst, nd)))
+    if (need > 0 && !own_ws && (ranges_overlap(ws, need, src, ns) || ranges_overlap(ws, need, dst, nd)))
         return DWT2_E_ALIAS;
     return DWT2_OK;
 }
@@ -350,6 +352,35 @@ int run_backward(dwt2::Direction dir, const void* src, void* dst, int32_t planes
     return DWT2_OK;
 }
 
+// Workspace of dwt2_fwd_noalloc: one fixed array per GPU (the code object
+// holds it on every device it is loaded on, until the process ends).  Host
+// code must not pass `scratch` itself to a kernel or a copy: in host code the
+// name is a host-side stand-in, not the device address.  The device address
+// is looked up once per device (hipGetSymbolAddress with that device
+// current) and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[DWT2_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+int scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return report(e);
+    if (dev < 0 || dev >= kMaxDevices) return report(hipErrorInvalidDevice);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return report(e);
+        if (!p) return report(hipErrorInvalidSymbol);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DWT2_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -430,6 +461,25 @@ int dwt2_adj(const void* src, void* dst, int32_t height, int32_t width, int64_t 
              void* stream) {
     return dwt2_adj_planes(src, dst, 1, 0, 0, height, width, src_pitch, dst_pitch, dtype, wavelet, levels, boundary,
                            flags, workspace, workspace_bytes, stream);
+}
+
+int dwt2_fwd_noalloc(const void* src, void* dst, int32_t height, int32_t width, int64_t src_pitch,
+                     int64_t dst_pitch, dwt2_dtype dtype, dwt2_wavelet wavelet, int levels,
+                     dwt2_boundary boundary, unsigned flags, void* stream) {
+    int rc = validate(src, dst, 1, 0, 0, height, width, src_pitch, dst_pitch, dtype, wavelet, levels, boundary,
+                      flags, nullptr, 0, false, /*own_ws=*/true);
+    if (rc) return rc;
+    size_t need = 0;
+    rc = dwt2_workspace_bytes(height, width, levels, dtype, &need);
+    if (rc) return rc;
+    if (need > DWT2_SCRATCH_BYTES) return DWT2_E_SCRATCH;
+    void* ws = nullptr;
+    if (need > 0) {                 // one level needs no workspace
+        rc = scratch_address(&ws);
+        if (rc) return rc;
+    }
+    return run_forward(src, dst, 1, 0, 0, height, width, src_pitch, dst_pitch, dtype, wavelet, levels, flags, ws,
+                       (hipStream_t)stream);
 }
 
 int dwt2_kernel_config(int index, int* algorithm, int* waves, int* rows, int* core_cols, int* core_rows) {
@@ -525,6 +575,7 @@ const char* dwt2_status_string(int status) {
         case DWT2_E_HIP: return "HIP runtime error";
         case DWT2_E_FLAGS: return "flags not valid for this call";
         case DWT2_E_COUNT: return "image count must be positive";
+        case DWT2_E_SCRATCH: return "the call needs more workspace than the library's fixed scratch array";
     }
     return "unknown status";
 }

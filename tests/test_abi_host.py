@@ -294,3 +294,26 @@ def test_lds_kernel_argument_rules():
     # the binding's table of supported cases agrees
     assert d.config_supports(lds[0], "fwd", "dd137") and not d.config_supports(tile[0], "fwd", "dd137")
     assert d.config_supports(lds[0], "inv", "cdf97", "polyconv") and not d.config_supports(lds[0], "adj", "cdf97")
+
+
+def test_noalloc_rejects_before_hip():
+    """dwt2_fwd_noalloc checks its arguments, and the fixed scratch size,
+    on the host before any HIP call (fake pointers: nothing may run)."""
+    def na(h=64, w=64, levels=2, dtype=d.DWT2_F32, wav=d.DWT2_CDF97, src=FAKE_SRC, dst=FAKE_DST, flags=0):
+        return d.dwt2_fwd_noalloc(ctypes.c_void_p(src), ctypes.c_void_p(dst), h, w, w, w, dtype, wav, levels, 0,
+                                  flags, None)
+    assert na(src=0) == -1
+    assert na(h=1) == -2
+    assert na(levels=9) == -3
+    assert na(dtype=d.DWT2_I32) == -4
+    assert na(flags=1 << 7) == -11
+    assert na(dst=FAKE_SRC + 64) == -9
+    # 16384^2 FP32 at 2 levels keeps an 8192^2 LL band (256 MiB): beyond the array
+    st, n = d.dwt2_workspace_bytes(16384, 16384, 2, d.DWT2_F32)
+    assert st == 0 and n > d.DWT2_SCRATCH_BYTES
+    assert na(h=16384, w=16384, levels=2, dst=FAKE_DST + (1 << 31)) == d.DWT2_E_SCRATCH
+    assert "scratch" in d.status_string(d.DWT2_E_SCRATCH)
+    # the largest case the array is sized for fits: 8192^2 FP32 at every level count
+    for lv in range(1, 14):
+        st, n = d.dwt2_workspace_bytes(8192, 8192, lv, d.DWT2_F32)
+        assert st == 0 and n <= d.DWT2_SCRATCH_BYTES
