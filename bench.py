@@ -330,6 +330,11 @@ def main():
         ws5 = d.workspace(N, N, 5, d.DWT2_F32, dev)
         form("cdf97 fwd f32 5 levels", lambda i, c: d.fwd(xs[i % pairs], "cdf97", 5, out=ys[i % pairs], config=c),
              5, 4, tune_key=("fwd", "cdf97", "f32"))
+        # the same 5 levels in one persistent launch (levels overlap; every
+        # tile publishes its LL rows to the other XCDs, results bit-identical)
+        form("cdf97 fwd f32 5 levels, one persistent launch",
+             lambda i, c: d.fwd(xs[i % pairs], "cdf97", 5, out=ys[i % pairs], config=c, persistent=True,
+                                workspace=ws5), 5, 4)
         form("cdf97 fwd f32 1 level split P0/P1",
              lambda i, c: d.fwd(xs[i % pairs], "cdf97", 1, split=True, out=ys[i % pairs], config=c), 1, 4,
              tune_key=None)
@@ -540,13 +545,16 @@ def main():
         del xa, tgt
         torch.cuda.empty_cache()
 
-        # batched, a planner launch plus one launch per level: 256 images with H, W uniform in [64, 4096] (even), 5 levels
-        def batched_form(name, shapes, seed, steps=5):
+        # batched: a planner launch plus one launch per level covering every
+        # image (or, persistent, one launch for every level of every image):
+        # 256 images with H, W uniform in [64, 4096] (even), 5 levels; 1024
+        # images of 256^2
+        def batched_form(name, shapes, seed, steps=5, persistent=False):
             if not want(name):
                 return
             g = torch.Generator(device=dev).manual_seed(seed)
             imgs = [torch.rand(s, device=dev, generator=g) for s in shapes]
-            call = d.BatchedForward(imgs, 5)
+            call = d.BatchedForward(imgs, 5, persistent=persistent)
             _, ms = time_steps(torch, lambda i: call.run(), steps, 2)
             # the same call captured once in a graph and replayed
             s2 = torch.cuda.Stream()
@@ -559,6 +567,8 @@ def main():
             with torch.cuda.graph(gr, stream=s2):
                 call.run()
             _, gms = time_steps(torch, lambda i: gr.replay(), steps, 2)
+            if persistent and call.status() != d.DWT2_OK:
+                raise RuntimeError(f"{name}: a dependency wait of the persistent launch ran out of time")
             npx = sum(h * w for h, w in shapes)
             ab = sum(algorithmic_bytes(h, w, 5, 4) for h, w in shapes)
             forms.append({"form": name, "Gpixel/s": round(npx / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
@@ -572,8 +582,13 @@ def main():
         batched_form("cdf97 fwd f32 5 levels, batched: 256 uneven images 64..4096",
                      workloads.uneven_shapes(256, 64, 4096, seed=1), seed=1)
         batched_form("cdf97 fwd f32 5 levels, batched: 1024 images 256x256", [(256, 256)] * 1024, seed=2, steps=10)
+        batched_form("cdf97 fwd f32 5 levels, batched, one persistent launch: 256 uneven images 64..4096",
+                     workloads.uneven_shapes(256, 64, 4096, seed=1), seed=1, steps=3, persistent=True)
+        batched_form("cdf97 fwd f32 5 levels, batched, one persistent launch: 1024 images 256x256",
+                     [(256, 256)] * 1024, seed=2, steps=5, persistent=True)
 
-        # the same 1024 equal-size images as one plane batch (one launch per level)
+        # the same 1024 equal-size images as one plane batch (one launch per
+        # level)
         pb_name = "cdf97 fwd f32 5 levels, plane batch: 1024 images 256x256"
         if want(pb_name):
             xp = torch.rand((1024, 256, 256), device=dev, generator=torch.Generator(device=dev).manual_seed(2))

@@ -72,8 +72,11 @@ typedef enum {
     DWT2_E_HIP = -10,       /* HIP runtime error at launch                      */
     DWT2_E_FLAGS = -11,     /* unknown flag, or flag not valid for the wavelet  */
     DWT2_E_COUNT = -12,     /* batched call: count < 1; plane batch: planes < 1 */
-    DWT2_E_SCRATCH = -13    /* dwt2_fwd_noalloc: the call needs more workspace
+    DWT2_E_SCRATCH = -13,   /* dwt2_fwd_noalloc: the call needs more workspace
                                than DWT2_SCRATCH_BYTES                          */
+    DWT2_E_TIMEOUT = -14    /* dwt2_workspace_status: a dependency wait of the
+                               persistent forward ran out of time; the outputs
+                               of that call are invalid                         */
 } dwt2_status;
 
 typedef enum {
@@ -139,6 +142,15 @@ typedef enum {
                                 forward / inverse on DWT2_ALGO_LDS kernel
                                 configurations (the default with this flag).
                                 Same values up to FP32 rounding.             */
+#define DWT2_FLAG_PERSISTENT 16u  /* dwt2_fwd / dwt2_fwd_planes /
+                                dwt2_fwd_batched: every level in one persistent
+                                launch (after a planner launch) instead of one
+                                launch per level; same values (bit-identical).
+                                CDF 9/7, fused or split steps, DWT2_ALGO_TILE
+                                configurations, at most 65536 planes; not for
+                                the inverse or adjoint (DWT2_E_FLAGS).  One
+                                level is one launch either way.  See
+                                dwt2_fwd_batched for its waits.              */
 /* Kernel configuration: bits 8..15 hold 1 + the index of a configuration
  * listed by dwt2_kernel_config(); 0 selects the library default.  Every
  * configuration computes the same values (bit-identical for the same other
@@ -177,14 +189,16 @@ typedef struct {
 int dwt2_max_levels(int32_t height, int32_t width);
 
 /* Device workspace (bytes) that dwt2_fwd / dwt2_inv / dwt2_adj need for this
- * shape, level count and storage type: two ping-pong buffers for the
- * intermediate LL bands (0 for one level).  Returns a dwt2_status. */
+ * shape, level count and storage type (0 for one level): the intermediate LL
+ * bands, and for the persistent forward also its work tables.  Returns a
+ * dwt2_status. */
 int dwt2_workspace_bytes(int32_t height, int32_t width, int levels,
                          dwt2_dtype dtype, size_t* bytes);
 
 /* Forward transform (Section "Proposed Schemes", non-separable lifting):
  * src = image (height x width, src_pitch), dst = Mallat pyramid
- * (height x width, dst_pitch).  Multi-level: levels >= 1. */
+ * (height x width, dst_pitch).  Multi-level: levels >= 1, one launch per
+ * level (DWT2_FLAG_PERSISTENT: one persistent launch for all levels). */
 int dwt2_fwd(const void* src, void* dst, int32_t height, int32_t width,
              int64_t src_pitch, int64_t dst_pitch, dwt2_dtype dtype,
              dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,
@@ -253,32 +267,46 @@ int dwt2_adj_planes(const void* src, void* dst, int32_t planes, int64_t src_plan
  * DWT2_OK or DWT2_E_FLAGS for an unknown index. */
 int dwt2_kernel_config(int index, int* algorithm, int* waves, int* rows, int* core_cols, int* core_rows);
 
-/* Device workspace (bytes) for dwt2_fwd_batched on these images: the work
- * tables (per level, each image's first tile; per image, the offset of its LL
- * buffers) and two LL ping-pong buffers per image.  `images` is a host array.
- * Returns a dwt2_status. */
+/* Device workspace (bytes) for dwt2_fwd_batched on these images, with or
+ * without DWT2_FLAG_PERSISTENT: the work tables and every image's
+ * intermediate LL bands.  `images` is a host array.  Returns a dwt2_status. */
 int dwt2_workspace_bytes_batched(const dwt2_image* images, int count, dwt2_dtype dtype, int levels,
                                  size_t* bytes);
 
 /* Batched forward CDF 9/7 (Section "Proposed Schemes", non-separable lifting,
  * applied to each image as dwt2_fwd would): `count` independent images of any
- * (uneven) sizes, every one transformed to `levels` levels, as one planner
- * launch plus one launch per level on `stream`; the launch of a level covers
- * the tiles of all images, so small images still fill the GPU.  The images
- * are given twice with identical contents: `host_images` (host memory, used
- * for the argument checks and the grid sizes) and `device_images` (device
- * memory, read by the kernels; it must stay valid until the launches have
- * run).  The call performs no copies or allocations and can be captured in a
- * graph.  Float storage (F32, BF16, F16); flags: DWT2_FLAG_SPLIT and a tile
- * kernel configuration (any DWT2_ALGO_TILE index of dwt2_kernel_config).  No image's
- * src or dst may overlap the workspace, and no image's dst may overlap the dst
- * or the src of any image (sources may overlap one another): every such batch
- * is rejected with DWT2_E_ALIAS.  The sum over the images of one level's tiles must stay
- * below 2^31 - 2^16 (else DWT2_E_SHAPE).  Results equal dwt2_fwd on each image
- * (bit-identical for the same configuration). */
+ * (uneven) sizes, every one transformed to `levels` levels, on `stream`.  By
+ * default a planner launch plus one launch per level, the launch of a level
+ * covering the tiles of all images.  With DWT2_FLAG_PERSISTENT: a planner
+ * launch plus one persistent launch for every level; its work-groups take
+ * tiles (of every image) from work queues, level after level, and a tile of
+ * level l >= 1 first waits until the tiles of level l - 1 whose LL rows it
+ * reads have finished, so the levels overlap.  Such a wait is bounded
+ * (200 ms; the environment variable DWT2_WAIT_LIMIT_US, read at each call,
+ * sets another limit): if one runs out the call still ends, with its outputs
+ * invalid and an error word set in the workspace (dwt2_workspace_status).
+ * The images are given twice with identical contents: `host_images` (host
+ * memory, used for the argument checks and the grid sizes) and
+ * `device_images` (device memory, read by the kernels; it must stay valid
+ * until the launches have run).  The call performs no copies or allocations
+ * and can be captured in a graph.  Float storage (F32, BF16, F16); flags:
+ * DWT2_FLAG_SPLIT, DWT2_FLAG_PERSISTENT and a tile kernel configuration (any
+ * DWT2_ALGO_TILE index of dwt2_kernel_config).  No image's src or dst may
+ * overlap the workspace, and no image's dst may overlap the dst or the src of
+ * any image (sources may overlap one another): every such batch is rejected
+ * with DWT2_E_ALIAS.  The sum over the images of one level's tiles must stay
+ * below 2^31 - 2^16 (else DWT2_E_SHAPE).  Results equal dwt2_fwd on each
+ * image (bit-identical for the same configuration). */
 int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_images, int count,
                      dwt2_dtype dtype, dwt2_wavelet wavelet, int levels, dwt2_boundary boundary,
                      unsigned flags, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Outcome of the last persistent forward (DWT2_FLAG_PERSISTENT) that used a
+ * workspace: `header` is a host copy of the first DWT2_WORKSPACE_STATUS_BYTES
+ * bytes of that workspace, taken after the call has run.  Returns DWT2_OK, or
+ * DWT2_E_TIMEOUT if a dependency wait ran out of time (outputs invalid). */
+#define DWT2_WORKSPACE_STATUS_BYTES 4
+int dwt2_workspace_status(const void* header);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops and harnesses that forbid hipMalloc): dwt2_fwd with
@@ -289,8 +317,9 @@ int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_ima
  * errors as dwt2_fwd (bit-identical results); a call that needs more
  * workspace than the array (dwt2_workspace_bytes) returns DWT2_E_SCRATCH
  * before any HIP call.  The first call on a device looks up the array's
- * address there (current device).  All calls on one GPU share its array and
- * nothing in it has to start at zero: calls ordered on one stream are safe,
+ * address there (current device).  All calls on one GPU share its array;
+ * what must start at zero there (the persistent path's counters) is cleared
+ * by each call's own planner launch: calls ordered on one stream are safe,
  * calls that can overlap in time on one GPU (other streams, other host
  * threads) race on it. */
 #define DWT2_SCRATCH_BYTES ((size_t)96 << 20)

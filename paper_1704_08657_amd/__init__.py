@@ -24,6 +24,8 @@ LIB_PATH = os.path.join(HERE, "libdwt2.so")
 DWT2_OK = 0
 DWT2_E_HIP = -10
 DWT2_E_SCRATCH = -13
+DWT2_E_TIMEOUT = -14
+DWT2_WORKSPACE_STATUS_BYTES = 4
 DWT2_SCRATCH_BYTES = 96 << 20
 DWT2_CDF97, DWT2_CDF53_REV, DWT2_CDF53, DWT2_DD137 = 0, 1, 2, 3
 DWT2_F32, DWT2_BF16, DWT2_F16, DWT2_I32 = 0, 1, 2, 3
@@ -32,6 +34,7 @@ DWT2_FLAG_SPLIT = 1
 DWT2_FLAG_SEPARABLE = 2
 DWT2_FLAG_FACTORED = 4
 DWT2_FLAG_POLYCONV = 8
+DWT2_FLAG_PERSISTENT = 16
 DWT2_FLAG_KERNEL_SHIFT = 8
 DWT2_NUM_KERNEL_CONFIGS = 10
 DWT2_ALGO_TILE, DWT2_ALGO_STREAM, DWT2_ALGO_LDS = 0, 1, 2
@@ -67,6 +70,7 @@ SIGNATURES = {
     "dwt2_fwd_batched": (_c_int, [_c_p, _c_p, _c_int, _c_int, _c_int, _c_int, _c_int, _c_u, _c_p, _c_sz, _c_p]),
     "dwt2_fwd_noalloc": (_c_int, [_c_p, _c_p, _c_i32, _c_i32, _c_i64, _c_i64, _c_int, _c_int, _c_int, _c_int,
                                   _c_u, _c_p]),
+    "dwt2_workspace_status": (_c_int, [_c_p]),
     "dwt2_status_string": (ctypes.c_char_p, [_c_int]),
     "dwt2_last_hip_error": (ctypes.c_char_p, []),
 }
@@ -217,8 +221,17 @@ def config_supports(index: int, direction: str, wavelet: str, scheme: str = "fus
     return True
 
 
+def workspace_status(ws) -> int:
+    """dwt2_workspace_status of a workspace tensor after the call that used
+    it has run: DWT2_OK, or DWT2_E_TIMEOUT if a dependency wait of the
+    persistent forward ran out of time (its outputs are then invalid).
+    Synchronises with the device (copies the status word to the host)."""
+    head = bytes(ws[:DWT2_WORKSPACE_STATUS_BYTES].cpu().numpy().tobytes())
+    return lib().dwt2_workspace_status(ctypes.c_char_p(head))
+
+
 def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=False, factored=False,
-               polyconv=False):
+               polyconv=False, persistent=False, ws=None):
     torch = _torch()
     _check(x)
     x2 = x.reshape(-1, *x.shape[-2:]) if x.is_contiguous() else x.contiguous().reshape(-1, *x.shape[-2:])
@@ -236,7 +249,8 @@ def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=
     dt = dtype_code(x2)
     stream = _stream_ptr(x2)
     flags = ((DWT2_FLAG_SPLIT if split else 0) | (DWT2_FLAG_SEPARABLE if separable else 0)
-             | (DWT2_FLAG_FACTORED if factored else 0) | (DWT2_FLAG_POLYCONV if polyconv else 0))
+             | (DWT2_FLAG_FACTORED if factored else 0) | (DWT2_FLAG_POLYCONV if polyconv else 0)
+             | (DWT2_FLAG_PERSISTENT if persistent else 0))
     if config is None:
         config = tuned_config(_DIRECTIONS[name], wavelet, dt, H, W, levels)
         scheme = ("split" if split else "separable" if separable else "factored" if factored
@@ -249,9 +263,9 @@ def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=
     step = (1 << 31) - 1
     for p0 in range(0, planes, step):
         n = min(step, planes - p0)
-        ws = workspace(H, W, levels, dt, x2.device, n)
-        ws_ptr = ctypes.c_void_p(ws.data_ptr() if ws is not None else 0)
-        ws_n = ws.numel() if ws is not None else 0
+        w = ws if ws is not None else workspace(H, W, levels, dt, x2.device, n)
+        ws_ptr = ctypes.c_void_p(w.data_ptr() if w is not None else 0)
+        ws_n = w.numel() if w is not None else 0
         st = fn(ctypes.c_void_p(x2[p0].data_ptr()), ctypes.c_void_p(out[p0].data_ptr()), n,
                 x2.stride(0), out.stride(0), H, W, x2.stride(-2), out.stride(-2), dt, WAVELETS[wavelet],
                 levels, DWT2_SYMMETRIC_WHOLE, flags, ws_ptr, ws_n, stream)
@@ -261,9 +275,13 @@ def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=
 
 
 def fwd(x, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None,
-        separable: bool = False, factored: bool = False, polyconv: bool = False):
+        separable: bool = False, factored: bool = False, polyconv: bool = False, persistent: bool = False,
+        workspace=None):
     """Forward transform of every [H, W] plane of x into a Mallat pyramid
-    (all planes in one call: one launch per level).  `config` selects a
+    (all planes in one call: one launch per level, or with `persistent` one
+    persistent launch for every level).  `workspace`: a uint8 device tensor of at least
+    dwt2_workspace_bytes_planes bytes to use instead of a fresh one (its
+    status can be read with workspace_status afterwards).  `config` selects a
     kernel configuration index (None: tuned or library default).  At most
     one of `split` (the P0/P1 operation-count reduction), `separable` (the
     separable comparison scheme, twice the barriers), `factored` (each
@@ -273,7 +291,7 @@ def fwd(x, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=Non
     Wavelets: "cdf97", "cdf53" (reversible integer), "cdf53f" (real CDF
     5/3), "dd137" (Deslauriers-Dubuc 13/7, LDS-plane kernel)."""
     return _transform(lib().dwt2_fwd_planes, "dwt2_fwd", x, wavelet, levels, split, out, config, separable,
-                      factored, polyconv)
+                      factored, polyconv, persistent, workspace)
 
 
 def inv(c, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None,
@@ -301,7 +319,7 @@ class BatchedForward:
     `run()` can be called repeatedly (or captured in a graph); `outs` are the
     Mallat pyramids, one per image."""
 
-    def __init__(self, images, levels: int, split: bool = False, config=None, outs=None):
+    def __init__(self, images, levels: int, split: bool = False, config=None, outs=None, persistent: bool = False):
         torch = _torch()
         if not images:
             raise ValueError("empty batch")
@@ -333,7 +351,8 @@ class BatchedForward:
             config = autotune.load_cache().get(
                 f"{autotune.arch_name()}|batched|cdf97|{_DTYPE_NAMES[self.dtype]}|any|5") \
                 if autotune.load_cache() else None
-        self.flags = (DWT2_FLAG_SPLIT if split else 0) | (DWT2_FLAG_KERNEL(config) if config is not None else 0)
+        self.flags = ((DWT2_FLAG_SPLIT if split else 0) | (DWT2_FLAG_PERSISTENT if persistent else 0)
+                      | (DWT2_FLAG_KERNEL(config) if config is not None else 0))
         n = len(images)
         self.host = (dwt2_image * n)()
         for i, (x, y) in enumerate(zip(self.images, self.outs)):
@@ -347,6 +366,10 @@ class BatchedForward:
             raise DWT2Error(st, "dwt2_workspace_bytes_batched")
         self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=images[0].device)
 
+    def status(self) -> int:
+        """dwt2_workspace_status of the last run (synchronises)."""
+        return workspace_status(self.workspace)
+
     def run(self):
         st = lib().dwt2_fwd_batched(ctypes.cast(self.host, ctypes.c_void_p), ctypes.c_void_p(self.device.data_ptr()),
                                     len(self.images), self.dtype, DWT2_CDF97, self.levels, DWT2_SYMMETRIC_WHOLE,
@@ -357,10 +380,11 @@ class BatchedForward:
         return self.outs
 
 
-def fwd_batched(images, levels: int = 1, split: bool = False, config=None, outs=None):
-    """Forward CDF 9/7 of a list of [H, W] images of any sizes (one planner
-    launch plus one launch per level); returns the list of Mallat pyramids."""
-    return BatchedForward(images, levels, split, config, outs).run()
+def fwd_batched(images, levels: int = 1, split: bool = False, config=None, outs=None, persistent: bool = False):
+    """Forward CDF 9/7 of a list of [H, W] images of any sizes (a planner
+    launch plus one launch per level, or with `persistent` one persistent
+    launch for every level); returns the list of Mallat pyramids."""
+    return BatchedForward(images, levels, split, config, outs, persistent).run()
 
 
 def _make_function():

@@ -146,6 +146,56 @@ dwt2::Scheme scheme_of(unsigned flags) {
     return dwt2::kSchemeFused;
 }
 
+// The persistent forward (DWT2_FLAG_PERSISTENT: every level in one launch)
+// runs CDF 9/7 with the fused or split steps on the tile configurations, for
+// plane stacks of at most kMaxPersistPlanes planes.
+constexpr int32_t kMaxPersistPlanes = 65536;
+
+bool persistent_ok(int wavelet, int dtype, unsigned flags, int32_t planes) {
+    return wavelet == DWT2_CDF97 && dtype != DWT2_I32 && planes <= kMaxPersistPlanes &&
+           !(flags & (DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED | DWT2_FLAG_POLYCONV)) &&
+           dwt2::persist_config_supported(config_of(flags, wavelet));
+}
+
+// Chunks and tiles of one image over all levels, for tile configuration cfg.
+void image_work(int32_t h, int32_t w, int levels, int cfg, uint64_t* chunks, uint64_t* tiles) {
+    const dwt2::KernelConfig c = dwt2::kConfigs[cfg];
+    *chunks = 0;
+    *tiles = 0;
+    for (int l = 0; l < levels; ++l) {
+        int32_t hl, wl, tx, ty;
+        dwt2::level_size(h, w, l, &hl, &wl);
+        dwt2::level_tiles(hl, wl, dwt2::core_cols(c), dwt2::core_rows(c), &tx, &ty);
+        *chunks += (uint64_t)dwt2::chunk_count(ty);
+        *tiles += (uint64_t)tx * (uint64_t)ty;
+    }
+}
+
+// Workspace of a persistent call on `count` images (a plane stack when
+// imgs == nullptr: `count` planes of h x w): the work tables and every
+// image's LL bands.  The tables depend on the tile shape, so the size is the
+// largest over the tile configurations.
+size_t persist_bytes(const dwt2_image* imgs, int count, int32_t h, int32_t w, int levels, size_t es) {
+    size_t tables = 0;
+    for (int cfg = 0; cfg < dwt2::kNumConfigs; ++cfg) {
+        if (!dwt2::persist_config_supported(cfg)) continue;
+        uint64_t chunks = 0;
+        for (int i = 0; i < (imgs ? count : 1); ++i) {
+            uint64_t c, t;
+            image_work(imgs ? imgs[i].height : h, imgs ? imgs[i].width : w, levels, cfg, &c, &t);
+            chunks += imgs ? c : c * (uint64_t)count;
+        }
+        const size_t off = dwt2::batch_layout(count, levels, chunks).off_ll;
+        tables = tables > off ? tables : off;
+    }
+    size_t ll = 0;
+    if (imgs)
+        for (int i = 0; i < count; ++i) ll += dwt2::image_ll_bytes(imgs[i].height, imgs[i].width, levels, es);
+    else
+        ll = (size_t)count * dwt2::image_ll_bytes(h, w, levels, es);
+    return tables + ll;
+}
+
 int validate(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dps, int32_t h, int32_t w,
              int64_t sp, int64_t dp, int dtype, int wavelet, int levels, int boundary, unsigned flags,
              const void* ws, size_t ws_bytes, bool adjoint, bool own_ws = false) {
@@ -158,7 +208,7 @@ int validate(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dp
     if ((wavelet == DWT2_CDF53_REV) != (dtype == DWT2_I32)) return DWT2_E_DTYPE;
     if (boundary != DWT2_SYMMETRIC_WHOLE) return DWT2_E_BOUNDARY;
     if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED | DWT2_FLAG_POLYCONV |
-                  DWT2_FLAG_KERNEL_MASK))
+                  DWT2_FLAG_PERSISTENT | DWT2_FLAG_KERNEL_MASK))
         return DWT2_E_FLAGS;
     if (((flags & DWT2_FLAG_KERNEL_MASK) >> DWT2_FLAG_KERNEL_SHIFT) > (unsigned)dwt2::kNumConfigs)
         return DWT2_E_FLAGS;
@@ -174,6 +224,8 @@ int validate(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dp
     if ((flags & (DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED)) && (adjoint || algo == dwt2::kAlgoStream))
         return DWT2_E_FLAGS;
     if ((flags & DWT2_FLAG_POLYCONV) && wavelet != DWT2_CDF97) return DWT2_E_FLAGS;
+    if ((flags & DWT2_FLAG_PERSISTENT) && (adjoint || !persistent_ok(wavelet, dtype, flags, planes)))
+        return DWT2_E_FLAGS;
     // the LDS-plane kernel: float wavelets, forward / inverse, fused,
     // separable and polyconvolution schemes; it alone runs DD 13/7 and the
     // polyconvolution
@@ -262,6 +314,16 @@ bool stride_ok(int32_t planes, int64_t stride, int v) { return planes == 1 || st
 int run_forward(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dps, int32_t h, int32_t w,
                 int64_t sp, int64_t dp, int dtype, int wavelet, int levels, unsigned flags, void* ws,
                 hipStream_t s) {
+    // one level is one launch either way (and needs no workspace)
+    if ((flags & DWT2_FLAG_PERSISTENT) && levels > 1) {
+        const int cfg = config_of(flags, wavelet);
+        uint64_t chunks, tiles;
+        image_work(h, w, levels, cfg, &chunks, &tiles);
+        const dwt2::ImageSet S{nullptr, src, dst, sps, dps, sp, dp, h, w};
+        const dwt2::BatchLayout L = dwt2::batch_layout(planes, levels, chunks * (uint64_t)planes);
+        return report(dwt2::launch_fwd_persistent(to_dtype(dtype), (flags & DWT2_FLAG_SPLIT) != 0, cfg, S, planes,
+                                                  levels, ws, L, tiles * (uint64_t)planes, s));
+    }
     Plan p;
     plan_levels(h, w, levels, &p);
     const size_t es = elem_size(dtype);
@@ -295,6 +357,9 @@ int run_forward(const void* src, void* dst, int32_t planes, int64_t sps, int64_t
         lp.vec8 = aligned(lp.in, 2 * es) && lp.in_pitch % 2 == 0 && stride_ok(planes, lp.in_ps, 2) &&
                   aligned(lp.out, 2 * es) && lp.out_pitch % 2 == 0 && stride_ok(planes, lp.out_ps, 2) &&
                   aligned(lp.out_ll, 2 * es) && lp.out_ll_pitch % 2 == 0 && stride_ok(planes, lp.out_ll_ps, 2);
+        // image rows 16-byte aligned
+        const int v16 = (int)(16 / es);
+        lp.vec16 = aligned(lp.in, 16) && lp.in_pitch % v16 == 0 && stride_ok(planes, lp.in_ps, v16);
         const int rc = launch_planes(dwt2::kForward, wavelet, dtype, flags, lp, planes, es, s);
         if (rc) return rc;
         in = lp.out_ll;
@@ -343,6 +408,9 @@ int run_backward(dwt2::Direction dir, const void* src, void* dst, int32_t planes
         lp.vec8 = aligned(lp.in, 2 * es) && lp.in_pitch % 2 == 0 && stride_ok(planes, lp.in_ps, 2) &&
                   aligned(lp.in_ll, 2 * es) && lp.in_ll_pitch % 2 == 0 && stride_ok(planes, lp.in_ll_ps, 2) &&
                   aligned(lp.out, 2 * es) && lp.out_pitch % 2 == 0 && stride_ok(planes, lp.out_ps, 2);
+        // image rows 16-byte aligned
+        const int v16 = (int)(16 / es);
+        lp.vec16 = aligned(lp.out, 16) && lp.out_pitch % v16 == 0 && stride_ok(planes, lp.out_ps, v16);
         const int rc = launch_planes(dir, wavelet, dtype, flags, lp, planes, es, s);
         if (rc) return rc;
         ll = lp.out;
@@ -398,7 +466,13 @@ int dwt2_workspace_bytes_planes(int32_t height, int32_t width, int levels, dwt2_
     if (levels < 1 || levels > max_levels(height, width)) return DWT2_E_LEVELS;
     Plan p;
     plan_levels(height, width, levels, &p);
-    *bytes = ws_layout(p, es, planes).total;
+    size_t n = ws_layout(p, es, planes).total;
+    // a float multi-level forward may take the persistent path
+    if (levels > 1 && dtype != DWT2_I32 && planes <= kMaxPersistPlanes) {
+        const size_t q = persist_bytes(nullptr, planes, height, width, levels, es);
+        n = n > q ? n : q;
+    }
+    *bytes = n;
     return DWT2_OK;
 }
 
@@ -421,6 +495,7 @@ int dwt2_inv_planes(const void* src, void* dst, int32_t planes, int64_t src_plan
                     int32_t height, int32_t width, int64_t src_pitch, int64_t dst_pitch, dwt2_dtype dtype,
                     dwt2_wavelet wavelet, int levels, dwt2_boundary boundary, unsigned flags, void* workspace,
                     size_t workspace_bytes, void* stream) {
+    if (flags & DWT2_FLAG_PERSISTENT) return DWT2_E_FLAGS;   // a forward-only path
     const int rc = validate(src, dst, planes, src_plane_stride, dst_plane_stride, height, width, src_pitch,
                             dst_pitch, dtype, wavelet, levels, boundary, flags, workspace, workspace_bytes, false);
     if (rc) return rc;
@@ -500,15 +575,18 @@ int dwt2_workspace_bytes_batched(const dwt2_image* images, int count, dwt2_dtype
     if (count < 1) return DWT2_E_COUNT;
     const size_t es = elem_size(dtype);
     if (!es) return DWT2_E_DTYPE;
-    const dwt2::BatchLayout L = dwt2::batch_layout(count, levels < 1 ? 1 : levels);
-    size_t total = L.off_ll;
     for (int i = 0; i < count; ++i) {
         const dwt2_image& im = images[i];
         if (im.height < 2 || im.width < 2 || im.height > kMaxSide || im.width > kMaxSide) return DWT2_E_SHAPE;
         if (levels < 1 || levels > max_levels(im.height, im.width)) return DWT2_E_LEVELS;
-        total += dwt2::image_ll_bytes(im.height, im.width, levels, es);
     }
-    *bytes = total;
+    // one launch per level: tile tables and ping-pong LL buffers; the
+    // persistent launch: work tables and one LL band per level
+    const dwt2::LevelBatchLayout L = dwt2::level_batch_layout(count, levels);
+    size_t n = L.off_ll;
+    for (int i = 0; i < count; ++i) n += dwt2::pingpong_ll_bytes(images[i].height, images[i].width, levels, es);
+    const size_t q = persist_bytes(images, count, 0, 0, levels, es);
+    *bytes = n > q ? n : q;
     return DWT2_OK;
 }
 
@@ -520,15 +598,14 @@ int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_ima
     if (wavelet != DWT2_CDF97) return DWT2_E_WAVELET;        // batched path: CDF 9/7
     if (dtype != DWT2_F32 && dtype != DWT2_BF16 && dtype != DWT2_F16) return DWT2_E_DTYPE;
     if (boundary != DWT2_SYMMETRIC_WHOLE) return DWT2_E_BOUNDARY;
-    if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_KERNEL_MASK)) return DWT2_E_FLAGS;
+    if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_PERSISTENT | DWT2_FLAG_KERNEL_MASK)) return DWT2_E_FLAGS;
     if (((flags & DWT2_FLAG_KERNEL_MASK) >> DWT2_FLAG_KERNEL_SHIFT) > (unsigned)dwt2::kNumConfigs)
         return DWT2_E_FLAGS;
     const int cfg = config_of(flags, wavelet);
-    if (!dwt2::batched_config_supported(cfg)) return DWT2_E_FLAGS;
+    if (!dwt2::persist_config_supported(cfg)) return DWT2_E_FLAGS;
     const size_t es = elem_size(dtype);
-    const int core = dwt2::core_rows(dwt2::kConfigs[cfg]);
-    const int core_x = dwt2::core_cols(dwt2::kConfigs[cfg]);
-    uint64_t tiles[32] = {0};
+    const dwt2::KernelConfig kc = dwt2::kConfigs[cfg];
+    uint64_t tiles[32] = {0}, chunks = 0, all_tiles = 0;
     for (int i = 0; i < count; ++i) {
         const dwt2_image& im = host_images[i];
         if (!im.src || !im.dst) return DWT2_E_NULL;
@@ -538,14 +615,18 @@ int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_ima
         if (ranges_overlap(im.src, span_bytes(im.height, im.width, im.src_pitch, es), im.dst,
                            span_bytes(im.height, im.width, im.dst_pitch, es)))
             return DWT2_E_ALIAS;
-        for (int l = 0; l < levels; ++l) tiles[l] += dwt2::level_tile_count(im.height, im.width, l, core_x, core);
+        for (int l = 0; l < levels; ++l)
+            tiles[l] += dwt2::level_tile_count(im.height, im.width, l, dwt2::core_cols(kc), dwt2::core_rows(kc));
+        uint64_t c, t;
+        image_work(im.height, im.width, levels, cfg, &c, &t);
+        chunks += c;
+        all_tiles += t;
     }
     if (batch_spans_alias(host_images, count, es)) return DWT2_E_ALIAS;
-    uint32_t tiles_per_level[32];
-    for (int l = 0; l < levels; ++l) {
-        if (tiles[l] > 0x7fff0000ull) return DWT2_E_SHAPE;     // grid of one launch
-        tiles_per_level[l] = (uint32_t)tiles[l];
-    }
+    // ticket numbers and counters are 32-bit
+    for (int l = 0; l < levels; ++l)
+        if (tiles[l] > 0x7fff0000ull) return DWT2_E_SHAPE;
+    if (chunks > 0x7fff0000ull) return DWT2_E_SHAPE;
     size_t need = 0;
     const int st = dwt2_workspace_bytes_batched(host_images, count, dtype, levels, &need);
     if (st) return st;
@@ -556,8 +637,22 @@ int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_ima
             ranges_overlap(workspace, need, im.dst, span_bytes(im.height, im.width, im.dst_pitch, es)))
             return DWT2_E_ALIAS;
     }
-    return report(dwt2::launch_fwd_batched(to_dtype(dtype), (flags & DWT2_FLAG_SPLIT) != 0, cfg, device_images,
-                                           count, levels, workspace, tiles_per_level, (hipStream_t)stream));
+    const bool split = (flags & DWT2_FLAG_SPLIT) != 0;
+    if ((flags & DWT2_FLAG_PERSISTENT) && levels > 1) {
+        const dwt2::ImageSet S{device_images, nullptr, nullptr, 0, 0, 0, 0, 0, 0};
+        const dwt2::BatchLayout L = dwt2::batch_layout(count, levels, chunks);
+        return report(dwt2::launch_fwd_persistent(to_dtype(dtype), split, cfg, S, count, levels, workspace, L,
+                                                  all_tiles, (hipStream_t)stream));
+    }
+    uint32_t tiles_per_level[32];
+    for (int l = 0; l < levels; ++l) tiles_per_level[l] = (uint32_t)tiles[l];
+    return report(dwt2::launch_fwd_batched_levels(to_dtype(dtype), split, cfg, device_images, count, levels,
+                                                  workspace, tiles_per_level, (hipStream_t)stream));
+}
+
+int dwt2_workspace_status(const void* header) {
+    if (!header) return DWT2_E_NULL;
+    return static_cast<const uint32_t*>(header)[0] != 0u ? DWT2_E_TIMEOUT : DWT2_OK;
 }
 
 const char* dwt2_status_string(int status) {
@@ -576,6 +671,7 @@ const char* dwt2_status_string(int status) {
         case DWT2_E_FLAGS: return "flags not valid for this call";
         case DWT2_E_COUNT: return "image count must be positive";
         case DWT2_E_SCRATCH: return "the call needs more workspace than the library's fixed scratch array";
+        case DWT2_E_TIMEOUT: return "a dependency wait of the persistent forward ran out of time: outputs invalid";
     }
     return "unknown status";
 }

@@ -62,11 +62,9 @@ constexpr KernelConfig kConfigs[] = {
 constexpr int kNumConfigs = 10;
 constexpr int kDefaultConfig = 0;
 constexpr int kDefaultLdsConfig = 8;
-// Tile kernels deal work over the 8 XCDs in chunks of kRemapRows tile rows
-// (a level) or kBatchChunk tiles (a batched launch); the grid is a multiple
-// of 8 chunks.
+// Tile kernels deal work over the 8 XCDs in chunks of kRemapRows tile rows;
+// the grid is a multiple of 8 chunks.
 constexpr int kRemapRows = 2;
-constexpr int kBatchChunk = 64;
 // output block rows / columns of one tile (kAlgoTile, kAlgoLds)
 constexpr int core_rows(KernelConfig c) { return c.algo == kAlgoLds ? c.cy : c.waves * c.rows - 2 * kHalo; }
 constexpr int core_cols(KernelConfig c) { return c.algo == kAlgoLds ? c.cx : kLanes * c.bpl; }
@@ -100,6 +98,10 @@ struct LevelParams {
     // (even pitches), so interior tiles can use pairs of samples (the
     // semi-vector interior path).
     int32_t vec8;
+    // With `vec`: the image rows (forward input, inverse / adjoint output)
+    // start 16-byte aligned, so 16-bit samples of 4 blocks per lane move as
+    // one 16-byte access per row.
+    int32_t vec16;
 };
 
 // Enqueue one level for `planes` planes (1 <= planes <= kMaxGridPlanes).
@@ -115,13 +117,5 @@ hipError_t launch_level(Direction dir, Wavelet wav, Dtype dt, Scheme scheme, int
 // of the float wavelets, fused / separable / polyconvolution schemes.
 hipError_t launch_lds(Direction dir, Wavelet wav, Dtype dt, Scheme scheme, int cfg, const LevelParams& p,
                       int planes, hipStream_t stream);
-
-// Batched forward CDF 9/7 (planner + one launch per level) for the tile
-// kernel configurations (batched_config_supported).
-// `tiles_per_level[l]` (host array of `levels` entries) is the number of
-// tiles of level l summed over the images: it sizes that level's grid.
-bool batched_config_supported(int cfg);
-hipError_t launch_fwd_batched(Dtype dt, bool split, int cfg, const dwt2_image* dev_imgs, int count, int levels,
-                              void* ws, const uint32_t* tiles_per_level, hipStream_t s);
 
 }  // namespace dwt2

@@ -84,7 +84,15 @@ template <> struct St<__hip_bfloat16> {
 template <> struct St<__half> {
     using V = float;
     __device__ static V load(__half v) { return __half2float(v); }
-    __device__ static __half store(V v) { return __float2half(v); }
+    // The conversion is one explicit instruction on the finished FP32 value,
+    // so the compiler cannot merge it with the multiply-add that produced
+    // the value (a mixed-precision FMA rounds once, straight to FP16, and in
+    // rare cases differs by one FP16 unit): every kernel rounds the same way.
+    __device__ static __half store(V v) {
+        unsigned r;
+        asm("v_cvt_f16_f32 %0, %1" : "=v"(r) : "v"(v));
+        return __ushort_as_half((unsigned short)r);
+    }
 };
 template <> struct St<int32_t> {
     using V = int;
@@ -92,6 +100,7 @@ template <> struct St<int32_t> {
     __device__ static int32_t store(V v) { return v; }
 };
 
+template <typename T> struct alignas(8 * sizeof(T)) Pack8 { T v[8]; };
 template <typename T> struct alignas(4 * sizeof(T)) Pack4 { T v[4]; };
 template <typename T> struct alignas(2 * sizeof(T)) Pack2 { T v[2]; };
 static_assert(sizeof(Pack4<float>) == 16 && sizeof(Pack2<__half>) == 4, "packed vector layout");
@@ -883,6 +892,19 @@ __device__ __forceinline__ void nt_store4(T* p, T a, T b, T c, T d) {
     }
 }
 
+// Eight 16-bit samples as one 16-byte nontemporal store.
+template <typename T>
+__device__ __forceinline__ void nt_store8(T* p, const T (&v)[8]) {
+    static_assert(sizeof(T) == 2, "16-bit samples");
+    typedef int v4 __attribute__((ext_vector_type(4)));
+    v4 q;
+    q.x = (int)((unsigned)__builtin_bit_cast(unsigned short, v[0]) | ((unsigned)__builtin_bit_cast(unsigned short, v[1]) << 16));
+    q.y = (int)((unsigned)__builtin_bit_cast(unsigned short, v[2]) | ((unsigned)__builtin_bit_cast(unsigned short, v[3]) << 16));
+    q.z = (int)((unsigned)__builtin_bit_cast(unsigned short, v[4]) | ((unsigned)__builtin_bit_cast(unsigned short, v[5]) << 16));
+    q.w = (int)((unsigned)__builtin_bit_cast(unsigned short, v[6]) | ((unsigned)__builtin_bit_cast(unsigned short, v[7]) << 16));
+    __builtin_nontemporal_store(q, reinterpret_cast<v4*>(p));
+}
+
 // Four consecutive samples of one image row starting at column c (a multiple
 // of 4); samples outside [0, w) or rows outside [0, h) read as 0.
 template <typename T, bool EDGE>
@@ -1030,15 +1052,38 @@ __device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][Lay<BPL>::BX
     for (int q = 0; q < 8; ++q) e[q] = V(0);
     if constexpr (DIR == kForward) {
         const T* in = static_cast<const T*>(P.in);
+        // 16-bit samples, 4 blocks per lane: a lane's 8 samples of an image
+        // row are one 16-byte load (rows 16-byte aligned: vec16)
+        bool wide = false;
+        if constexpr (!EDGE && sizeof(T) == 2 && BPL == 4) {
+            wide = P.vec16 != 0;
+            if (wide) {
 #pragma unroll
-        for (int r = 0; r < K; ++r) {
-            const int row = 2 * (g.gr0 + r);
+                for (int r = 0; r < K; ++r)
 #pragma unroll
-            for (int q = 0; q < BPL / 2; ++q) {
-                const int c = 2 * g.gcL + 4 * q;
-                V* b0 = &a[r][8 * q];
-                load4<T, EDGE>(in, P.in_pitch, row, c, P.h, P.w, vec, b0[0], b0[1], b0[4], b0[5]);
-                load4<T, EDGE>(in, P.in_pitch, row + 1, c, P.h, P.w, vec, b0[2], b0[3], b0[6], b0[7]);
+                    for (int h = 0; h < 2; ++h) {
+                        const Pack8<T> q = *reinterpret_cast<const Pack8<T>*>(
+                            in + (int64_t)(2 * (g.gr0 + r) + h) * P.in_pitch + 2 * g.gcL);
+                        // samples 2j, 2j+1 of the row: block j, components 2h, 2h+1
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            a[r][4 * j + 2 * h] = St<T>::load(q.v[2 * j]);
+                            a[r][4 * j + 2 * h + 1] = St<T>::load(q.v[2 * j + 1]);
+                        }
+                    }
+            }
+        }
+        if (!wide) {
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                const int row = 2 * (g.gr0 + r);
+#pragma unroll
+                for (int q = 0; q < BPL / 2; ++q) {
+                    const int c = 2 * g.gcL + 4 * q;
+                    V* b0 = &a[r][8 * q];
+                    load4<T, EDGE>(in, P.in_pitch, row, c, P.h, P.w, vec, b0[0], b0[1], b0[4], b0[5]);
+                    load4<T, EDGE>(in, P.in_pitch, row + 1, c, P.h, P.w, vec, b0[2], b0[3], b0[6], b0[7]);
+                }
             }
         }
         if (halo_lane) {
@@ -1234,12 +1279,30 @@ __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::B
             }
     } else {
         T* img = static_cast<T*>(P.out);
+        bool wide = false;
+        if constexpr (!EDGE && sizeof(T) == 2 && BPL == 4) wide = P.vec16 != 0;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
             const int tr = wv * K + r;
             if (tr < kHalo || tr >= kHalo + kCoreBY) continue;
             const int gr = g.gr0 + r;
             if (EDGE && gr >= g.nEr) continue;
+            if constexpr (!EDGE && sizeof(T) == 2 && BPL == 4) {
+                if (wide) {
+                    // 16-bit samples, 4 blocks per lane: one 16-byte store per image row
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        T o[8];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            o[2 * j] = St<T>::store(a[r][4 * j + 2 * h]);
+                            o[2 * j + 1] = St<T>::store(a[r][4 * j + 2 * h + 1]);
+                        }
+                        nt_store8(img + (int64_t)(2 * gr + h) * P.out_pitch + 2 * g.gcL, o);
+                    }
+                    continue;
+                }
+            }
 #pragma unroll
             for (int q = 0; q < BPL / 2; ++q) {
                 const int c = 2 * g.gcL + 4 * q;

@@ -1,9 +1,7 @@
-// Host check of the tile work plans (dwt2_batch_plan.h, and the level
-// kernel's tile remap): on random batches
-// of uneven images, every tile of every image at every level is covered
-// exactly once by the per-level grids (with the XCD remap of the batched
-// level kernel), the work tables fit below the LL area, and every
-// intermediate LL band read or written stays inside its own buffer.
+// Host check of the tile work plans of one launch per level: the level
+// kernel's tile remap (for many tile grids and plane counts, the grid of one
+// level launch covers every tile of every plane exactly once) and the
+// batched level kernel's plan (dwt2_batch_plan.h).
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -12,9 +10,14 @@
 #include <random>
 #include "dwt2_batch_plan.h"
 using namespace dwt2;
+// Batched forward, one launch per level: on random batches of uneven
+// images, every tile of every image at every level is covered exactly once
+// by the per-level grids (with the batched level kernel's XCD remap), the
+// work tables fit below the LL area, and every intermediate LL band read or
+// written stays inside its own ping-pong buffer.
 int run(const std::vector<int>& H, const std::vector<int>& W, int levels, int cx, int core, size_t es) {
     int count = H.size(); int bad = 0;
-    BatchLayout L = batch_layout(count, levels);
+    LevelBatchLayout L = level_batch_layout(count, levels);
     std::vector<uint32_t> off((size_t)levels * (count + 1));
     for (int l = 0; l < levels; ++l) {
         uint32_t c = 0;
@@ -22,19 +25,19 @@ int run(const std::vector<int>& H, const std::vector<int>& W, int levels, int cx
         off[l*(count+1)+count] = c;
     }
     size_t llsum = 0; std::vector<size_t> llo(count);
-    for (int i = 0; i < count; ++i) { llo[i] = llsum; llsum += image_ll_bytes(H[i], W[i], levels, es); }
+    for (int i = 0; i < count; ++i) { llo[i] = llsum; llsum += pingpong_ll_bytes(H[i], W[i], levels, es); }
     // tables inside workspace before LL area
     if (L.off_tile + sizeof(uint32_t)*off.size() > L.off_ll_off) bad++;
     if (L.off_ll_off + 8*(size_t)count > L.off_ll) bad++;
     for (int l = 0; l < levels; ++l) {
         uint32_t total = off[l*(count+1)+count];
-        const uint32_t chunks = (total + kBatchChunk - 1) / kBatchChunk;
-        const uint32_t grid = (chunks + 7) / 8 * 8 * kBatchChunk;
+        const uint32_t chunks = (total + kLevelChunk - 1) / kLevelChunk;
+        const uint32_t grid = (chunks + 7) / 8 * 8 * kLevelChunk;
         std::vector<std::vector<int>> seen(count);
         for (int i = 0; i < count; ++i) seen[i].assign(level_tile_count(H[i], W[i], l, cx, core), 0);
         for (uint32_t b = 0; b < grid; ++b) {
             const uint32_t j = b >> 3;
-            const uint32_t t = ((j / kBatchChunk) * 8 + (b & 7)) * kBatchChunk + j % kBatchChunk;
+            const uint32_t t = ((j / kLevelChunk) * 8 + (b & 7)) * kLevelChunk + j % kLevelChunk;
             if (t >= total) continue;
             const uint32_t* o = &off[l*(count+1)];
             int lo = 0, hi = count;
@@ -44,8 +47,8 @@ int run(const std::vector<int>& H, const std::vector<int>& W, int levels, int cx
             seen[lo][tt]++;
             // buffer bounds: in / out_ll of this level inside the LL area
             int32_t hl, wl; level_size(H[lo], W[lo], l, &hl, &wl);
-            size_t A = llo[lo], B = A + image_ll_b_offset(H[lo], W[lo], levels, es);
-            size_t endimg = llo[lo] + image_ll_bytes(H[lo], W[lo], levels, es);
+            size_t A = llo[lo], B = A + pingpong_b_offset(H[lo], W[lo], levels, es);
+            size_t endimg = llo[lo] + pingpong_ll_bytes(H[lo], W[lo], levels, es);
             if (l > 0) {  // input: hl rows of wl elements at pitch ll_pitch(wl)
                 size_t base = (l-1)%2==0 ? A : B;
                 size_t lastend = base + ((size_t)(hl-1)*ll_pitch(wl) + wl) * es;

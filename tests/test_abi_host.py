@@ -47,11 +47,18 @@ def test_workspace_bytes():
         m = ctypes.c_size_t(1)
         assert d.lib().dwt2_workspace_bytes_planes(h, w, 1, d.DWT2_F32, planes, ctypes.byref(m)) == 0
         assert m.value == 0
+    # a float multi-level forward runs persistently: the LL band of every
+    # level but the last (4096^2, 2048^2, 1024^2, 512^2, pitches multiple of
+    # 64) plus the work tables, which for one image fit in a few KiB
+    bands = 4096 * 4096 + 2048 * 2048 + 1024 * 1024 + 512 * 512
     st, n = d.dwt2_workspace_bytes(8192, 8192, 5, d.DWT2_F32)
-    # LL of level 1 (4096 x 4096) and level 2 (2048 x 2048), pitch multiple of 64
-    assert st == 0 and n == 4096 * 4096 * 4 + 2048 * 2048 * 4
+    assert st == 0 and bands * 4 <= n <= bands * 4 + 16384
     st, n = d.dwt2_workspace_bytes(8192, 8192, 5, d.DWT2_BF16)
-    assert st == 0 and n == (4096 * 4096 + 2048 * 2048) * 2
+    assert st == 0 and bands * 2 <= n <= bands * 2 + 16384
+    # int32 (reversible 5/3) keeps the two ping-pong buffers of the level
+    # launches: LL of level 1 (4096^2) and level 2 (2048^2)
+    st, n = d.dwt2_workspace_bytes(8192, 8192, 5, d.DWT2_I32)
+    assert st == 0 and n == 4096 * 4096 * 4 + 2048 * 2048 * 4
     st, _ = d.dwt2_workspace_bytes(8192, 8192, 14, d.DWT2_F32)
     assert st == -3
     st, _ = d.dwt2_workspace_bytes(1, 8, 1, d.DWT2_F32)
@@ -83,7 +90,7 @@ def test_argument_errors(fn):
     assert call(fn, levels=7) == -3          # 64 x 64 allows 6
     assert call(fn, boundary=1) == -6
     assert call(fn, dtype=7) == -4
-    assert call(fn, flags=16) == -11
+    assert call(fn, flags=1 << 7) == -11
     # workspace required for 2 levels
     assert call(fn, levels=2) == -8
     assert call(fn, levels=2, ws=FAKE_WS, ws_n=10) == -8
@@ -238,7 +245,13 @@ def test_plane_batch_argument_errors():
     assert L.dwt2_workspace_bytes_planes(64, 64, 2, d.DWT2_F32, 3, ctypes.byref(n)) == 0
     one = ctypes.c_size_t(0)
     assert L.dwt2_workspace_bytes_planes(64, 64, 2, d.DWT2_F32, 1, ctypes.byref(one)) == 0
-    assert n.value == 3 * one.value > 0               # one pair of LL buffers per plane
+    # every plane keeps its own LL bands (plus the persistent forward's
+    # work tables, which grow with the plane count)
+    assert n.value >= 3 * (32 * 64 * 4) and n.value > one.value > 0
+    ni, onei = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.dwt2_workspace_bytes_planes(64, 64, 2, d.DWT2_I32, 3, ctypes.byref(ni)) == 0
+    assert L.dwt2_workspace_bytes_planes(64, 64, 2, d.DWT2_I32, 1, ctypes.byref(onei)) == 0
+    assert ni.value == 3 * onei.value > 0             # int32: one LL buffer pair per plane
     assert L.dwt2_workspace_bytes_planes(64, 64, 2, d.DWT2_F32, 0, ctypes.byref(n)) == -12
     need = L.dwt2_workspace_bytes_planes(64, 64, 2, d.DWT2_F32, 3, ctypes.byref(n)) or n.value
 
@@ -317,3 +330,19 @@ def test_noalloc_rejects_before_hip():
     for lv in range(1, 14):
         st, n = d.dwt2_workspace_bytes(8192, 8192, lv, d.DWT2_F32)
         assert st == 0 and n <= d.DWT2_SCRATCH_BYTES
+
+
+def test_persistent_flag_rules():
+    """DWT2_FLAG_PERSISTENT: forward CDF 9/7, fused or split steps, tile
+    configurations; every other use is rejected on the host (fake pointers)."""
+    P = d.DWT2_FLAG_PERSISTENT
+    st, n = d.dwt2_workspace_bytes(64, 64, 3, d.DWT2_F32)
+    assert st == 0 and n > 0
+    for fn in (d.dwt2_inv, d.dwt2_adj):
+        assert call(fn, flags=P, levels=3, ws=FAKE_WS, ws_n=n) == -11
+    assert call(flags=P, levels=3, dtype=d.DWT2_I32, wav=d.DWT2_CDF53_REV, ws=FAKE_WS, ws_n=n) == -11
+    assert call(flags=P | d.DWT2_FLAG_SEPARABLE, levels=3, ws=FAKE_WS, ws_n=n) == -11
+    assert call(flags=P | d.DWT2_FLAG_FACTORED, levels=3, ws=FAKE_WS, ws_n=n) == -11
+    stream_cfg = next(i for i in range(d.DWT2_NUM_KERNEL_CONFIGS) if d.dwt2_kernel_config(i)[1] == d.DWT2_ALGO_STREAM)
+    assert call(flags=P | d.DWT2_FLAG_KERNEL(stream_cfg), levels=3, ws=FAKE_WS, ws_n=n) == -11
+    assert call(flags=P, levels=3, ws=FAKE_WS, ws_n=n - 1) == -8     # the persistent tables need the full workspace
