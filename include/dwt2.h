@@ -142,12 +142,23 @@ typedef enum {
                                 forward / inverse on DWT2_ALGO_LDS kernel
                                 configurations (the default with this flag).
                                 Same values up to FP32 rounding.             */
+#define DWT2_FLAG_FUSED 32u  /* the fused steps T_P, S_U evaluated directly (the
+                                paper's formulas).  Without any scheme flag the
+                                fused steps run, evaluated directly for 4-byte
+                                samples, and for BF16 / FP16 storage on
+                                DWT2_ALGO_TILE configurations in the factored
+                                form of DWT2_FLAG_FACTORED (same steps and
+                                barriers, fewer operations: with half the bytes
+                                per pixel that kernel is bound by its
+                                arithmetic); this flag asks for the direct
+                                evaluation everywhere.  Not together with
+                                another scheme flag.                         */
 #define DWT2_FLAG_PERSISTENT 16u  /* dwt2_fwd / dwt2_fwd_planes /
                                 dwt2_fwd_batched: every level in one persistent
                                 launch (after a planner launch) instead of one
                                 launch per level; same values (bit-identical).
-                                CDF 9/7, fused or split steps, DWT2_ALGO_TILE
-                                configurations, at most 65536 planes; not for
+                                CDF 9/7, fused, split or factored steps,
+                                DWT2_ALGO_TILE configurations, at most 65536 planes; not for
                                 the inverse or adjoint (DWT2_E_FLAGS).  One
                                 level is one launch either way.  See
                                 dwt2_fwd_batched for its waits.              */

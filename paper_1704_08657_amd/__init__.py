@@ -35,6 +35,7 @@ DWT2_FLAG_SEPARABLE = 2
 DWT2_FLAG_FACTORED = 4
 DWT2_FLAG_POLYCONV = 8
 DWT2_FLAG_PERSISTENT = 16
+DWT2_FLAG_FUSED = 32
 DWT2_FLAG_KERNEL_SHIFT = 8
 DWT2_NUM_KERNEL_CONFIGS = 10
 DWT2_ALGO_TILE, DWT2_ALGO_STREAM, DWT2_ALGO_LDS = 0, 1, 2
@@ -231,7 +232,7 @@ def workspace_status(ws) -> int:
 
 
 def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=False, factored=False,
-               polyconv=False, persistent=False, ws=None):
+               polyconv=False, persistent=False, ws=None, fused=False):
     torch = _torch()
     _check(x)
     x2 = x.reshape(-1, *x.shape[-2:]) if x.is_contiguous() else x.contiguous().reshape(-1, *x.shape[-2:])
@@ -250,7 +251,7 @@ def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=
     stream = _stream_ptr(x2)
     flags = ((DWT2_FLAG_SPLIT if split else 0) | (DWT2_FLAG_SEPARABLE if separable else 0)
              | (DWT2_FLAG_FACTORED if factored else 0) | (DWT2_FLAG_POLYCONV if polyconv else 0)
-             | (DWT2_FLAG_PERSISTENT if persistent else 0))
+             | (DWT2_FLAG_PERSISTENT if persistent else 0) | (DWT2_FLAG_FUSED if fused else 0))
     if config is None:
         config = tuned_config(_DIRECTIONS[name], wavelet, dt, H, W, levels)
         scheme = ("split" if split else "separable" if separable else "factored" if factored
@@ -276,7 +277,7 @@ def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=
 
 def fwd(x, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None,
         separable: bool = False, factored: bool = False, polyconv: bool = False, persistent: bool = False,
-        workspace=None):
+        workspace=None, fused: bool = False):
     """Forward transform of every [H, W] plane of x into a Mallat pyramid
     (all planes in one call: one launch per level, or with `persistent` one
     persistent launch for every level).  `workspace`: a uint8 device tensor of at least
@@ -291,14 +292,14 @@ def fwd(x, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=Non
     Wavelets: "cdf97", "cdf53" (reversible integer), "cdf53f" (real CDF
     5/3), "dd137" (Deslauriers-Dubuc 13/7, LDS-plane kernel)."""
     return _transform(lib().dwt2_fwd_planes, "dwt2_fwd", x, wavelet, levels, split, out, config, separable,
-                      factored, polyconv, persistent, workspace)
+                      factored, polyconv, persistent, workspace, fused)
 
 
 def inv(c, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None,
-        separable: bool = False, factored: bool = False, polyconv: bool = False):
+        separable: bool = False, factored: bool = False, polyconv: bool = False, fused: bool = False):
     """Inverse transform of every [H, W] Mallat pyramid of c."""
     return _transform(lib().dwt2_inv_planes, "dwt2_inv", c, wavelet, levels, split, out, config, separable,
-                      factored, polyconv)
+                      factored, polyconv, fused=fused)
 
 
 def adj(g, levels: int = 1, out=None, config=None):

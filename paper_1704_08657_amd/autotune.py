@@ -110,7 +110,8 @@ def _time(torch, fn, steps=20, warm=4):
     return a.elapsed_time(b) / steps
 
 
-def tune(sizes=(256, 1024, 4096, 8192), levels=(1, 5), quick=False, out=CACHE_PATH, log=print):
+def tune(sizes=(256, 1024, 4096, 8192), levels=(1, 5), quick=False, out=CACHE_PATH, log=print,
+         dtypes=("f32", "bf16", "f16", "i32")):
     import torch
     import paper_1704_08657_amd as d
 
@@ -122,10 +123,13 @@ def tune(sizes=(256, 1024, 4096, 8192), levels=(1, 5), quick=False, out=CACHE_PA
     for n in sizes:
         for lv in levels:
             for dt in (("f32", "bf16") if quick else ("f32", "bf16", "f16")):
+                if dt not in dtypes:
+                    continue
                 cases += [("fwd", "cdf97", dt, n, lv), ("inv", "cdf97", dt, n, lv)]
                 if dt == "f32":
                     cases.append(("adj", "cdf97", dt, n, lv))
-            cases += [("fwd", "cdf53", "i32", n, lv), ("inv", "cdf53", "i32", n, lv)]
+            if "i32" in dtypes:
+                cases += [("fwd", "cdf53", "i32", n, lv), ("inv", "cdf53", "i32", n, lv)]
     nconf = d.DWT2_NUM_KERNEL_CONFIGS
     for direction, wav, dt, n, lv in cases:
         g = torch.Generator(device=dev).manual_seed(0)
@@ -142,7 +146,9 @@ def tune(sizes=(256, 1024, 4096, 8192), levels=(1, 5), quick=False, out=CACHE_PA
               "adj": lambda x, y, c: d.adj(x, lv, out=y, config=c)}[direction]
         best, best_ms = None, float("inf")
         for c in range(nconf):
-            if not d.config_supports(c, direction, wav):
+            # the LDS-plane configurations run what the register tile kernel
+            # does not (and are never faster where both run)
+            if not d.config_supports(c, direction, wav) or d.dwt2_kernel_config(c)[1] == d.DWT2_ALGO_LDS:
                 continue
             ms = _time(torch, lambda i: fn(xs[i % nb], ys[i % nb], c), steps=8 if quick else 30)
             if ms < best_ms:
@@ -151,7 +157,7 @@ def tune(sizes=(256, 1024, 4096, 8192), levels=(1, 5), quick=False, out=CACHE_PA
         result[k] = best
         log(f"{k}: config {best} ({best_ms * 1e3:.1f} us)")
     # batched: between the configurations the batched kernels support
-    for dt in ("f32", "bf16"):
+    for dt in [t for t in ("f32", "bf16") if t in dtypes]:
         shapes = [(int(h), int(w)) for h, w in zip(*[iter(
             torch.randint(32, 2049, (64,), generator=torch.Generator().manual_seed(1)).mul(2).tolist())] * 2)]
         imgs = [torch.rand(s, device=dev).to(dts[dt]) for s in shapes]
@@ -176,10 +182,11 @@ def main():
     ap.add_argument("--out", default=CACHE_PATH)
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--sizes", default="256,1024,4096,8192")
+    ap.add_argument("--dtypes", default="f32,bf16,f16,i32", help="storage types to tune (the others keep their entries)")
     a = ap.parse_args()
     t0 = time.time()
     tune(sizes=tuple(int(s) for s in a.sizes.split(",")), quick=a.quick, out=a.out,
-         log=lambda s: print(s, flush=True))
+         log=lambda s: print(s, flush=True), dtypes=tuple(a.dtypes.split(",")))
     print(f"tuned in {time.time() - t0:.1f} s -> {a.out}", flush=True)
 
 

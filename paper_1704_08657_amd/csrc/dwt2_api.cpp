@@ -138,11 +138,22 @@ int config_of(unsigned flags, int wavelet) {
     return (wavelet == DWT2_DD137 || (flags & DWT2_FLAG_POLYCONV)) ? dwt2::kDefaultLdsConfig : dwt2::kDefaultConfig;
 }
 
-dwt2::Scheme scheme_of(unsigned flags) {
+// Lifting scheme of a call.  Without a scheme flag: the fused steps,
+// evaluated directly (T_P, S_U) for 4-byte samples, and for BF16 / FP16
+// storage on the tile configurations as their two 1-D factors in registers
+// (the same steps and barriers, 8 instead of 11 operations per block and
+// step): with half the bytes per pixel that kernel is bound by its
+// arithmetic.  DWT2_FLAG_FUSED asks for the direct evaluation everywhere.
+dwt2::Scheme scheme_of(unsigned flags, int dtype, int wavelet, bool adjoint) {
     if (flags & DWT2_FLAG_SPLIT) return dwt2::kSchemeSplit;
     if (flags & DWT2_FLAG_SEPARABLE) return dwt2::kSchemeSeparable;
     if (flags & DWT2_FLAG_FACTORED) return dwt2::kSchemeFactored;
     if (flags & DWT2_FLAG_POLYCONV) return dwt2::kSchemePolyconv;
+    if (flags & DWT2_FLAG_FUSED) return dwt2::kSchemeFused;
+    const bool half = dtype == DWT2_BF16 || dtype == DWT2_F16;
+    if (half && !adjoint && (wavelet == DWT2_CDF97 || wavelet == DWT2_CDF53) &&
+        dwt2::kConfigs[config_of(flags, wavelet)].algo == dwt2::kAlgoTile)
+        return dwt2::kSchemeFactored;
     return dwt2::kSchemeFused;
 }
 
@@ -153,7 +164,7 @@ constexpr int32_t kMaxPersistPlanes = 65536;
 
 bool persistent_ok(int wavelet, int dtype, unsigned flags, int32_t planes) {
     return wavelet == DWT2_CDF97 && dtype != DWT2_I32 && planes <= kMaxPersistPlanes &&
-           !(flags & (DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED | DWT2_FLAG_POLYCONV)) &&
+           !(flags & (DWT2_FLAG_SEPARABLE | DWT2_FLAG_POLYCONV)) &&
            dwt2::persist_config_supported(config_of(flags, wavelet));
 }
 
@@ -208,7 +219,7 @@ int validate(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dp
     if ((wavelet == DWT2_CDF53_REV) != (dtype == DWT2_I32)) return DWT2_E_DTYPE;
     if (boundary != DWT2_SYMMETRIC_WHOLE) return DWT2_E_BOUNDARY;
     if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED | DWT2_FLAG_POLYCONV |
-                  DWT2_FLAG_PERSISTENT | DWT2_FLAG_KERNEL_MASK))
+                  DWT2_FLAG_FUSED | DWT2_FLAG_PERSISTENT | DWT2_FLAG_KERNEL_MASK))
         return DWT2_E_FLAGS;
     if (((flags & DWT2_FLAG_KERNEL_MASK) >> DWT2_FLAG_KERNEL_SHIFT) > (unsigned)dwt2::kNumConfigs)
         return DWT2_E_FLAGS;
@@ -218,7 +229,8 @@ int validate(const void* src, void* dst, int32_t planes, int64_t sps, int64_t dp
     // inverse on tile configurations (the separable one also on LDS-plane
     // configurations); the polyconvolution: CDF 9/7 forward / inverse on
     // LDS-plane configurations
-    const unsigned schemes = flags & (DWT2_FLAG_SPLIT | DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED | DWT2_FLAG_POLYCONV);
+    const unsigned schemes =
+        flags & (DWT2_FLAG_SPLIT | DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED | DWT2_FLAG_POLYCONV | DWT2_FLAG_FUSED);
     if (schemes & (schemes - 1)) return DWT2_E_FLAGS;
     const int algo = dwt2::kConfigs[config_of(flags, wavelet)].algo;
     if ((flags & (DWT2_FLAG_SEPARABLE | DWT2_FLAG_FACTORED)) && (adjoint || algo == dwt2::kAlgoStream))
@@ -296,7 +308,8 @@ int launch_planes(dwt2::Direction dir, int wavelet, int dtype, unsigned flags, d
             q.out = lp.out ? (char*)lp.out + (size_t)p0 * (size_t)lp.out_ps * es : nullptr;
             q.out_ll = lp.out_ll ? (char*)lp.out_ll + (size_t)p0 * (size_t)lp.out_ll_ps * es : nullptr;
         }
-        const int rc = report(dwt2::launch_level(dir, to_wav(wavelet), to_dtype(dtype), scheme_of(flags),
+        const int rc = report(dwt2::launch_level(dir, to_wav(wavelet), to_dtype(dtype),
+                                                 scheme_of(flags, dtype, wavelet, dir == dwt2::kAdjoint),
                                                  config_of(flags, wavelet), q, n, s));
         if (rc) return rc;
     }
@@ -321,8 +334,8 @@ int run_forward(const void* src, void* dst, int32_t planes, int64_t sps, int64_t
         image_work(h, w, levels, cfg, &chunks, &tiles);
         const dwt2::ImageSet S{nullptr, src, dst, sps, dps, sp, dp, h, w};
         const dwt2::BatchLayout L = dwt2::batch_layout(planes, levels, chunks * (uint64_t)planes);
-        return report(dwt2::launch_fwd_persistent(to_dtype(dtype), (flags & DWT2_FLAG_SPLIT) != 0, cfg, S, planes,
-                                                  levels, ws, L, tiles * (uint64_t)planes, s));
+        return report(dwt2::launch_fwd_persistent(to_dtype(dtype), scheme_of(flags, dtype, wavelet, false), cfg, S,
+                                                  planes, levels, ws, L, tiles * (uint64_t)planes, s));
     }
     Plan p;
     plan_levels(h, w, levels, &p);
@@ -598,7 +611,13 @@ int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_ima
     if (wavelet != DWT2_CDF97) return DWT2_E_WAVELET;        // batched path: CDF 9/7
     if (dtype != DWT2_F32 && dtype != DWT2_BF16 && dtype != DWT2_F16) return DWT2_E_DTYPE;
     if (boundary != DWT2_SYMMETRIC_WHOLE) return DWT2_E_BOUNDARY;
-    if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_PERSISTENT | DWT2_FLAG_KERNEL_MASK)) return DWT2_E_FLAGS;
+    if (flags & ~(DWT2_FLAG_SPLIT | DWT2_FLAG_FACTORED | DWT2_FLAG_FUSED | DWT2_FLAG_PERSISTENT |
+                  DWT2_FLAG_KERNEL_MASK))
+        return DWT2_E_FLAGS;
+    {
+        const unsigned sch = flags & (DWT2_FLAG_SPLIT | DWT2_FLAG_FACTORED | DWT2_FLAG_FUSED);
+        if (sch & (sch - 1)) return DWT2_E_FLAGS;          // at most one scheme
+    }
     if (((flags & DWT2_FLAG_KERNEL_MASK) >> DWT2_FLAG_KERNEL_SHIFT) > (unsigned)dwt2::kNumConfigs)
         return DWT2_E_FLAGS;
     const int cfg = config_of(flags, wavelet);
@@ -637,16 +656,16 @@ int dwt2_fwd_batched(const dwt2_image* host_images, const dwt2_image* device_ima
             ranges_overlap(workspace, need, im.dst, span_bytes(im.height, im.width, im.dst_pitch, es)))
             return DWT2_E_ALIAS;
     }
-    const bool split = (flags & DWT2_FLAG_SPLIT) != 0;
+    const dwt2::Scheme sch = scheme_of(flags, dtype, wavelet, false);
     if ((flags & DWT2_FLAG_PERSISTENT) && levels > 1) {
         const dwt2::ImageSet S{device_images, nullptr, nullptr, 0, 0, 0, 0, 0, 0};
         const dwt2::BatchLayout L = dwt2::batch_layout(count, levels, chunks);
-        return report(dwt2::launch_fwd_persistent(to_dtype(dtype), split, cfg, S, count, levels, workspace, L,
+        return report(dwt2::launch_fwd_persistent(to_dtype(dtype), sch, cfg, S, count, levels, workspace, L,
                                                   all_tiles, (hipStream_t)stream));
     }
     uint32_t tiles_per_level[32];
     for (int l = 0; l < levels; ++l) tiles_per_level[l] = (uint32_t)tiles[l];
-    return report(dwt2::launch_fwd_batched_levels(to_dtype(dtype), split, cfg, device_images, count, levels,
+    return report(dwt2::launch_fwd_batched_levels(to_dtype(dtype), sch, cfg, device_images, count, levels,
                                                   workspace, tiles_per_level, (hipStream_t)stream));
 }
 

@@ -235,18 +235,18 @@ struct ImageSet {
 constexpr int kWaitLimitMs = 200;
 
 // Planner plus one launch per level for a tile kernel configuration
-// (persist_config_supported), CDF 9/7 forward, fused or split steps, float
-// storage; `tiles_per_level[l]` (host array) is the number of tiles of level l
+// (persist_config_supported), CDF 9/7 forward, fused, split or factored
+// steps, float storage; `tiles_per_level[l]` (host array) is the number of tiles of level l
 // summed over the images and sizes that level's grid.
-hipError_t launch_fwd_batched_levels(Dtype dt, bool split, int cfg, const dwt2_image* dev_imgs, int count,
+hipError_t launch_fwd_batched_levels(Dtype dt, Scheme sch, int cfg, const dwt2_image* dev_imgs, int count,
                                      int levels, void* ws, const uint32_t* tiles_per_level, hipStream_t s);
 
 // Planner plus persistent kernel for a tile kernel configuration
-// (persist_config_supported), CDF 9/7 forward with the fused or split
-// steps, float storage.  `BL` from batch_layout with the chunks of this
+// (persist_config_supported), CDF 9/7 forward with the fused, split or
+// factored steps, float storage.  `BL` from batch_layout with the chunks of this
 // configuration, `tiles` the tiles of all levels and images.
 bool persist_config_supported(int cfg);
-hipError_t launch_fwd_persistent(Dtype dt, bool split, int cfg, const ImageSet& S, int count, int levels, void* ws,
+hipError_t launch_fwd_persistent(Dtype dt, Scheme sch, int cfg, const ImageSet& S, int count, int levels, void* ws,
                                  const BatchLayout& BL, uint64_t tiles, hipStream_t s);
 
 }  // namespace dwt2

@@ -292,8 +292,14 @@ batched_level_kernel(const dwt2_image* imgs, int count, int levels, int l, unsig
     const int ty = tt / P.tiles_x;
     const int tx = tt - ty * P.tiles_x;
     // images whose rows are only 8-byte aligned: semi-vector interior tiles
-    if (!P.vec && P.vec8) tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, true>(P, tx, ty, lds, lane, wv);
-    else tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, false>(P, tx, ty, lds, lane, wv);
+    // (fused and split steps, as the level kernel)
+    if constexpr (SCH == kSchemeFused || SCH == kSchemeSplit) {
+        if (!P.vec && P.vec8) {
+            tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, true>(P, tx, ty, lds, lane, wv);
+            return;
+        }
+    }
+    tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, false>(P, tx, ty, lds, lane, wv);
 }
 
 // ---- one persistent launch -------------------------------------------------
@@ -431,8 +437,11 @@ persist_fwd_kernel(ImageSet S, int count, int levels, BatchLayout BL, uint64_t w
         P.vec8 = is_aligned(P.in, 2 * es) && P.in_pitch % 2 == 0 && is_aligned(P.out, 2 * es) &&
                  P.out_pitch % 2 == 0 && is_aligned(P.out_ll, 2 * es) && P.out_ll_pitch % 2 == 0;
         P.vec16 = is_aligned(P.in, 16) && P.in_pitch % (int64_t)(16 / es) == 0;
-        // images whose rows are only 8-byte aligned: semi-vector interior tiles
-        if (!P.vec && P.vec8) tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, true>(P, tcol, trow, lds, lane, wv);
+        // images whose rows are only 8-byte aligned: semi-vector interior
+        // tiles (fused and split steps, as the level kernel)
+        bool semi = false;
+        if constexpr (SCH == kSchemeFused || SCH == kSchemeSplit) semi = !P.vec && P.vec8;
+        if (semi) tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, true>(P, tcol, trow, lds, lane, wv);
         else tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, false>(P, tcol, trow, lds, lane, wv);
 
         // publish the tile: every thread's stores, then the chunk counter
@@ -551,10 +560,14 @@ hipError_t launch_levels_cfg(int cfg, const dwt2_image* d, int count, int levels
 }
 
 template <typename T>
-hipError_t launch_levels_t(bool split, int cfg, const dwt2_image* d, int count, int levels, void* ws,
+hipError_t launch_levels_t(Scheme sch, int cfg, const dwt2_image* d, int count, int levels, void* ws,
                            const uint32_t* tpl, hipStream_t s) {
-    return split ? launch_levels_cfg<T, kSchemeSplit>(cfg, d, count, levels, ws, tpl, s)
-                 : launch_levels_cfg<T, kSchemeFused>(cfg, d, count, levels, ws, tpl, s);
+    switch (sch) {
+        case kSchemeFused: return launch_levels_cfg<T, kSchemeFused>(cfg, d, count, levels, ws, tpl, s);
+        case kSchemeSplit: return launch_levels_cfg<T, kSchemeSplit>(cfg, d, count, levels, ws, tpl, s);
+        case kSchemeFactored: return launch_levels_cfg<T, kSchemeFactored>(cfg, d, count, levels, ws, tpl, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T, int SCH>
@@ -577,10 +590,15 @@ hipError_t launch_persist_cfg(int cfg, const ImageSet& S, int count, int levels,
 }
 
 template <typename T>
-hipError_t launch_persist_t(bool split, int cfg, const ImageSet& S, int count, int levels, void* ws,
+hipError_t launch_persist_t(Scheme sch, int cfg, const ImageSet& S, int count, int levels, void* ws,
                             const BatchLayout& BL, uint64_t tiles, hipStream_t s) {
-    return split ? launch_persist_cfg<T, kSchemeSplit>(cfg, S, count, levels, ws, BL, tiles, s)
-                 : launch_persist_cfg<T, kSchemeFused>(cfg, S, count, levels, ws, BL, tiles, s);
+    switch (sch) {
+        case kSchemeFused: return launch_persist_cfg<T, kSchemeFused>(cfg, S, count, levels, ws, BL, tiles, s);
+        case kSchemeSplit: return launch_persist_cfg<T, kSchemeSplit>(cfg, S, count, levels, ws, BL, tiles, s);
+        case kSchemeFactored:
+            return launch_persist_cfg<T, kSchemeFactored>(cfg, S, count, levels, ws, BL, tiles, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -588,23 +606,23 @@ hipError_t launch_persist_t(bool split, int cfg, const ImageSet& S, int count, i
 
 bool persist_config_supported(int cfg) { return cfg >= 0 && cfg < kNumConfigs && kConfigs[cfg].algo == kAlgoTile; }
 
-hipError_t launch_fwd_batched_levels(Dtype dt, bool split, int cfg, const dwt2_image* dev_imgs, int count,
+hipError_t launch_fwd_batched_levels(Dtype dt, Scheme sch, int cfg, const dwt2_image* dev_imgs, int count,
                                      int levels, void* ws, const uint32_t* tiles_per_level, hipStream_t s) {
     switch (dt) {
-        case kF32: return kern::launch_levels_t<float>(split, cfg, dev_imgs, count, levels, ws, tiles_per_level, s);
+        case kF32: return kern::launch_levels_t<float>(sch, cfg, dev_imgs, count, levels, ws, tiles_per_level, s);
         case kBF16:
-            return kern::launch_levels_t<__hip_bfloat16>(split, cfg, dev_imgs, count, levels, ws, tiles_per_level, s);
-        case kF16: return kern::launch_levels_t<__half>(split, cfg, dev_imgs, count, levels, ws, tiles_per_level, s);
+            return kern::launch_levels_t<__hip_bfloat16>(sch, cfg, dev_imgs, count, levels, ws, tiles_per_level, s);
+        case kF16: return kern::launch_levels_t<__half>(sch, cfg, dev_imgs, count, levels, ws, tiles_per_level, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_fwd_persistent(Dtype dt, bool split, int cfg, const ImageSet& S, int count, int levels, void* ws,
+hipError_t launch_fwd_persistent(Dtype dt, Scheme sch, int cfg, const ImageSet& S, int count, int levels, void* ws,
                                  const BatchLayout& BL, uint64_t tiles, hipStream_t s) {
     switch (dt) {
-        case kF32: return kern::launch_persist_t<float>(split, cfg, S, count, levels, ws, BL, tiles, s);
-        case kBF16: return kern::launch_persist_t<__hip_bfloat16>(split, cfg, S, count, levels, ws, BL, tiles, s);
-        case kF16: return kern::launch_persist_t<__half>(split, cfg, S, count, levels, ws, BL, tiles, s);
+        case kF32: return kern::launch_persist_t<float>(sch, cfg, S, count, levels, ws, BL, tiles, s);
+        case kBF16: return kern::launch_persist_t<__hip_bfloat16>(sch, cfg, S, count, levels, ws, BL, tiles, s);
+        case kF16: return kern::launch_persist_t<__half>(sch, cfg, S, count, levels, ws, BL, tiles, s);
         default: return hipErrorInvalidValue;
     }
 }

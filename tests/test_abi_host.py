@@ -91,6 +91,7 @@ def test_argument_errors(fn):
     assert call(fn, boundary=1) == -6
     assert call(fn, dtype=7) == -4
     assert call(fn, flags=1 << 7) == -11
+    assert call(fn, flags=d.DWT2_FLAG_FUSED | d.DWT2_FLAG_FACTORED) == -11   # one scheme at most
     # workspace required for 2 levels
     assert call(fn, levels=2) == -8
     assert call(fn, levels=2, ws=FAKE_WS, ws_n=10) == -8
@@ -333,8 +334,9 @@ def test_noalloc_rejects_before_hip():
 
 
 def test_persistent_flag_rules():
-    """DWT2_FLAG_PERSISTENT: forward CDF 9/7, fused or split steps, tile
-    configurations; every other use is rejected on the host (fake pointers)."""
+    """DWT2_FLAG_PERSISTENT: forward CDF 9/7, fused, split or factored steps,
+    tile configurations; every other use is rejected on the host (fake
+    pointers)."""
     P = d.DWT2_FLAG_PERSISTENT
     st, n = d.dwt2_workspace_bytes(64, 64, 3, d.DWT2_F32)
     assert st == 0 and n > 0
@@ -342,7 +344,8 @@ def test_persistent_flag_rules():
         assert call(fn, flags=P, levels=3, ws=FAKE_WS, ws_n=n) == -11
     assert call(flags=P, levels=3, dtype=d.DWT2_I32, wav=d.DWT2_CDF53_REV, ws=FAKE_WS, ws_n=n) == -11
     assert call(flags=P | d.DWT2_FLAG_SEPARABLE, levels=3, ws=FAKE_WS, ws_n=n) == -11
-    assert call(flags=P | d.DWT2_FLAG_FACTORED, levels=3, ws=FAKE_WS, ws_n=n) == -11
+    assert call(flags=P | d.DWT2_FLAG_POLYCONV, levels=3, ws=FAKE_WS, ws_n=n) == -11
+    assert call(flags=P | d.DWT2_FLAG_FUSED | d.DWT2_FLAG_SPLIT, levels=3, ws=FAKE_WS, ws_n=n) == -11
     stream_cfg = next(i for i in range(d.DWT2_NUM_KERNEL_CONFIGS) if d.dwt2_kernel_config(i)[1] == d.DWT2_ALGO_STREAM)
     assert call(flags=P | d.DWT2_FLAG_KERNEL(stream_cfg), levels=3, ws=FAKE_WS, ws_n=n) == -11
     assert call(flags=P, levels=3, ws=FAKE_WS, ws_n=n - 1) == -8     # the persistent tables need the full workspace

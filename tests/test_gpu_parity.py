@@ -230,13 +230,25 @@ def test_kernel_configs_bit_identical():
             x = gpu(workloads.pixels_u8(h, w, seed=4))
         else:
             x = gpu(workloads.uniform(h, w, seed=4)).to(tdt)
-        ref_f = d.fwd(x, wav, lv, split=split, config=0)
-        ref_i = d.inv(ref_f, wav, lv, split=split, config=0)
+        # 16-bit storage runs the factored evaluation by default on the tile
+        # configurations only; across every configuration the direct fused
+        # evaluation is compared (and the default across the tile ones below)
+        half = tdt in (torch.bfloat16, torch.float16)
+        ref_f = d.fwd(x, wav, lv, split=split, config=0, fused=half)
+        ref_i = d.inv(ref_f, wav, lv, split=split, config=0, fused=half)
+        if half:
+            dflt_f = d.fwd(x, wav, lv, config=0)
+            dflt_i = d.inv(dflt_f, wav, lv, config=0)
+            for sh in tile_configs()[1:]:
+                say("kernel config (16-bit default)", sh, wav, tdt, (h, w), lv)
+                f = d.fwd(x, wav, lv, config=sh)
+                assert torch.equal(f, dflt_f), sh
+                assert torch.equal(d.inv(f, wav, lv, config=sh), dflt_i), sh
         for sh in range(1, d.DWT2_NUM_KERNEL_CONFIGS):
             if not d.config_supports(sh, "fwd", wav, "split" if split else "fused"):
                 continue                  # the LDS-plane kernel runs neither the split nor the integer 5/3
             say("kernel config", sh, wav, tdt, (h, w), lv, split)
-            f = d.fwd(x, wav, lv, split=split, config=sh)
+            f = d.fwd(x, wav, lv, split=split, config=sh, fused=half)
             if split:
                 # The split (P = P0 + P1, U = U0 + U1) runs in interior tiles
                 # only, and which tiles are interior depends on the tile
@@ -246,7 +258,7 @@ def test_kernel_configs_bit_identical():
                 assert rel_err(host(f), host(ref_f)) <= 1e-5
             else:
                 assert torch.equal(f, ref_f)
-                assert torch.equal(d.inv(f, wav, lv, config=sh), ref_i)
+                assert torch.equal(d.inv(f, wav, lv, config=sh, fused=half), ref_i)
         if wav == "cdf97" and tdt == torch.float32 and not split:
             g = ref_f
             a0 = d.adj(g, lv, config=0)
@@ -346,16 +358,17 @@ def test_plane_batch_equals_single_planes(shape, lv):
 
 
 # ---- the semi-vector interior path (rows only 8-byte aligned) ---------------
-def fwd_pitched(x, wavelet, lv, dst_pitch, config):
+def fwd_pitched(x, wavelet, lv, dst_pitch, config, flags=0):
     """Forward through the raw C ABI into a destination of row pitch
-    `dst_pitch` (elements); returns the h x w pyramid."""
+    `dst_pitch` (elements), with `flags` besides the configuration; returns
+    the h x w pyramid."""
     h, w = x.shape
     dt = d.dtype_code(x)
     dst = torch.zeros((h, dst_pitch), dtype=x.dtype, device=dev())
     ws = d.workspace(h, w, lv, dt, dev())
     wsp = ctypes.c_void_p(ws.data_ptr() if ws is not None else 0)
     st = d.dwt2_fwd(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(dst.data_ptr()), h, w, w, dst_pitch,
-                    dt, d.WAVELETS[wavelet], lv, 0, d.DWT2_FLAG_KERNEL(config), wsp,
+                    dt, d.WAVELETS[wavelet], lv, 0, d.DWT2_FLAG_KERNEL(config) | flags, wsp,
                     ws.numel() if ws is not None else 0, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert st == 0, st
     return dst[:, :w]
@@ -373,18 +386,21 @@ def test_semi_vector_path_bit_identical(shape):
     xi = gpu(workloads.pixels_u8(h, w, seed=62))
     ref = lifting.fwd(host(xf), "cdf97", 3)
     for cfg in tile_configs():
-        for x, wav in ((xf, "cdf97"), (xf.to(torch.bfloat16), "cdf97"), (xf, "cdf53f"), (xi, "cdf53")):
+        # BF16 twice: with the direct fused evaluation (which has the
+        # semi-vector path) and with the default factored one
+        for x, wav, fl in ((xf, "cdf97", 0), (xf.to(torch.bfloat16), "cdf97", d.DWT2_FLAG_FUSED),
+                           (xf.to(torch.bfloat16), "cdf97", 0), (xf, "cdf53f", 0), (xi, "cdf53", 0)):
             for lv in (1, 3):
-                say("semi-vector path", shape, cfg, wav, x.dtype, lv)
-                even = fwd_pitched(x, wav, lv, w + 2 if w % 4 == 0 else w, cfg)
-                odd = fwd_pitched(x, wav, lv, w + 1, cfg)
+                say("semi-vector path", shape, cfg, wav, x.dtype, fl, lv)
+                even = fwd_pitched(x, wav, lv, w + 2 if w % 4 == 0 else w, cfg, fl)
+                odd = fwd_pitched(x, wav, lv, w + 1, cfg, fl)
                 assert torch.equal(even, odd), (cfg, wav, x.dtype, lv)
-                assert torch.equal(even, d.fwd(x, wav, lv, config=cfg)), (cfg, wav, x.dtype, lv)
+                assert torch.equal(even, d.fwd(x, wav, lv, config=cfg, fused=fl != 0)), (cfg, wav, x.dtype, lv)
         y = fwd_pitched(xf, "cdf97", 3, w, cfg)
         assert rel_err(host(y), ref) <= TOL97, cfg
 
 
-def back_pitched(fn, c, wavelet, lv, src_pitch, config):
+def back_pitched(fn, c, wavelet, lv, src_pitch, config, flags=0):
     """Inverse or adjoint through the raw C ABI from a source of row pitch
     `src_pitch` (elements) holding the pyramid c; returns the h x w image."""
     h, w = c.shape
@@ -395,7 +411,7 @@ def back_pitched(fn, c, wavelet, lv, src_pitch, config):
     ws = d.workspace(h, w, lv, dt, dev())
     wsp = ctypes.c_void_p(ws.data_ptr() if ws is not None else 0)
     st = fn(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), h, w, src_pitch, w,
-            dt, d.WAVELETS[wavelet], lv, 0, d.DWT2_FLAG_KERNEL(config), wsp,
+            dt, d.WAVELETS[wavelet], lv, 0, d.DWT2_FLAG_KERNEL(config) | flags, wsp,
             ws.numel() if ws is not None else 0, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert st == 0, st
     return dst
@@ -413,13 +429,14 @@ def test_semi_vector_path_inverse_adjoint_bit_identical(shape):
     cg = gpu(c)
     ci = gpu(lifting.fwd(workloads.pixels_u8(h, w, seed=64), "cdf53", 3).astype(np.int32))
     for cfg in tile_configs():
-        for cc, wav in ((cg, "cdf97"), (cg.to(torch.bfloat16), "cdf97"), (cg, "cdf53f"), (ci, "cdf53")):
+        for cc, wav, fl in ((cg, "cdf97", 0), (cg.to(torch.bfloat16), "cdf97", d.DWT2_FLAG_FUSED),
+                            (cg.to(torch.bfloat16), "cdf97", 0), (cg, "cdf53f", 0), (ci, "cdf53", 0)):
             for lv in (1, 3):
-                say("semi-vector inverse", shape, cfg, wav, cc.dtype, lv)
-                even = back_pitched(d.dwt2_inv, cc, wav, lv, w + 2 if w % 4 == 0 else w, cfg)
-                odd = back_pitched(d.dwt2_inv, cc, wav, lv, w + 1, cfg)
+                say("semi-vector inverse", shape, cfg, wav, cc.dtype, fl, lv)
+                even = back_pitched(d.dwt2_inv, cc, wav, lv, w + 2 if w % 4 == 0 else w, cfg, fl)
+                odd = back_pitched(d.dwt2_inv, cc, wav, lv, w + 1, cfg, fl)
                 assert torch.equal(even, odd), (cfg, wav, cc.dtype, lv)
-                assert torch.equal(even, d.inv(cc, wav, lv, config=cfg)), (cfg, wav, cc.dtype, lv)
+                assert torch.equal(even, d.inv(cc, wav, lv, config=cfg, fused=fl != 0)), (cfg, wav, cc.dtype, lv)
         say("semi-vector adjoint", shape, cfg)
         even = back_pitched(d.dwt2_adj, cg, "cdf97", 3, w + 2 if w % 4 == 0 else w, cfg)
         odd = back_pitched(d.dwt2_adj, cg, "cdf97", 3, w + 1, cfg)
