@@ -1133,13 +1133,16 @@ __device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][Lay<BPL>::BX
 }
 
 // Whole-point symmetric extension of a sample index p into [0, n), n >= 2:
-// symmetric about both ends, hence periodic with period 2 (n - 1).
+// symmetric about both ends, hence periodic with period 2 (n - 1).  Reflected
+// about the nearer end until inside: one reflection for every index at most
+// n - 1 outside (all of a tile's halo once n > 8); each further pair of
+// reflections moves the index 2 (n - 1) closer, so tiny images take a few
+// more.  The loop is a handful of instructions where the period's modulo
+// (an integer division) is a few dozen at every inlined call site.
 __device__ __forceinline__ int reflect(int p, int n) {
-    if (p >= 0 && p < n) return p;
-    const int period = 2 * (n - 1);
-    int q = p % period;
-    if (q < 0) q += period;
-    return q < n ? q : period - q;
+    int q = p;
+    while (q < 0 || q >= n) q = q < 0 ? -q : 2 * (n - 1) - q;
+    return q;
 }
 
 // Border tiles of the forward and inverse transforms: the tile is loaded
@@ -1531,16 +1534,30 @@ __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
 
 // The level parameters of plane `pl` of a plane batch (buffers offset by
 // the plane strides).
+// Branch-free: a buffer the direction does not use (null) may move by its
+// stride, and is never dereferenced.  Pointer arithmetic (not integer
+// casts) keeps the buffers in the global address space for the compiler, so
+// accesses stay global_load / global_store rather than flat ones.
 template <typename T>
 __device__ __forceinline__ LevelParams plane_params(const LevelParams& P, int pl) {
     LevelParams Q = P;
-    if (pl > 0) {
-        if (P.in) Q.in = static_cast<const T*>(P.in) + (int64_t)pl * P.in_ps;
-        if (P.in_ll) Q.in_ll = static_cast<const T*>(P.in_ll) + (int64_t)pl * P.in_ll_ps;
-        if (P.out) Q.out = static_cast<T*>(P.out) + (int64_t)pl * P.out_ps;
-        if (P.out_ll) Q.out_ll = static_cast<T*>(P.out_ll) + (int64_t)pl * P.out_ll_ps;
-    }
+    Q.in = static_cast<const T*>(P.in) + (int64_t)pl * P.in_ps;
+    Q.in_ll = static_cast<const T*>(P.in_ll) + (int64_t)pl * P.in_ll_ps;
+    Q.out = static_cast<T*>(P.out) + (int64_t)pl * P.out_ps;
+    Q.out_ll = static_cast<T*>(P.out_ll) + (int64_t)pl * P.out_ll_ps;
     return Q;
+}
+
+// Every field of the level parameters is taken into SGPRs here, before the
+// first branch and before any value derived from them: the scalar loads of
+// the kernel arguments then go out together and cost one memory round trip
+// per wave, where loads issued at each field's first use (after the tile
+// index arithmetic, inside the plane-offset code) cost three or four.
+__device__ __forceinline__ void fetch_params(const LevelParams& P) {
+    asm volatile("" ::"s"(P.in), "s"(P.in_pitch), "s"(P.in_ll), "s"(P.in_ll_pitch), "s"(P.out), "s"(P.out_pitch),
+                 "s"(P.out_ll), "s"(P.out_ll_pitch), "s"(P.h), "s"(P.w), "s"(P.tiles_x), "s"(P.tiles_y), "s"(P.vec),
+                 "s"(P.in_ps), "s"(P.in_ll_ps), "s"(P.out_ps), "s"(P.out_ll_ps), "s"(P.planes), "s"(P.vec8),
+                 "s"(P.vec16));
 }
 
 template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL, bool SEMI>
@@ -1550,6 +1567,7 @@ __global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
     const int lane = threadIdx.x & (kLanes - 1);
     // the wave index is uniform: keep it (and every row address) in SGPRs
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+    fetch_params(P);
     // Work-groups are dealt round-robin over the 8 XCDs.  XCD x takes chunks
     // x, x + 8, x + 16, ... of kRemapRows whole tile rows: horizontal halo
     // re-reads stay in that XCD's L2 (and vertical ones within a chunk),
