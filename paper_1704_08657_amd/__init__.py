@@ -150,13 +150,19 @@ def _torch():
     return torch
 
 
+_dtype_codes = None
+
+
 def dtype_code(t) -> int:
-    torch = _torch()
-    codes = {torch.float32: DWT2_F32, torch.bfloat16: DWT2_BF16,
-             torch.float16: DWT2_F16, torch.int32: DWT2_I32}
-    if t.dtype not in codes:
+    global _dtype_codes
+    if _dtype_codes is None:
+        torch = _torch()
+        _dtype_codes = {torch.float32: DWT2_F32, torch.bfloat16: DWT2_BF16,
+                        torch.float16: DWT2_F16, torch.int32: DWT2_I32}
+    code = _dtype_codes.get(t.dtype)
+    if code is None:
         raise TypeError(f"unsupported dtype {t.dtype}")
-    return codes[t.dtype]
+    return code
 
 
 def _check(x):
@@ -170,6 +176,9 @@ def _check(x):
 
 def _stream_ptr(x):
     torch = _torch()
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)   # the current stream's handle, without a Stream object
+    if raw is not None:
+        return ctypes.c_void_p(raw(x.device.index))
     return ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
 
 
@@ -199,11 +208,26 @@ def tuned_config(direction: str, wavelet: str, dtype: int, h: int, w: int, level
     """Kernel configuration the autotuner recorded for this case, or None
     (looked up once per case and size class: small transforms are bound by
     the per-call host time)."""
+    k0 = (direction, wavelet, dtype, h, w, levels)
+    if k0 in _tuned:                      # this exact case seen before
+        return _tuned[k0]
     from . import autotune
     k = (direction, wavelet, dtype, autotune.size_class(h, w), levels)
     if k not in _tuned:
         _tuned[k] = autotune.lookup(direction, wavelet, _DTYPE_NAMES[dtype], h, w, levels)
+    _tuned[k0] = _tuned[k]
     return _tuned[k]
+
+
+_supports = {}
+
+
+def _config_ok(index: int, direction: str, wavelet: str, scheme: str) -> bool:
+    k = (index, direction, wavelet, scheme)
+    r = _supports.get(k)
+    if r is None:
+        r = _supports[k] = config_supports(index, direction, wavelet, scheme)
+    return r
 
 
 def config_supports(index: int, direction: str, wavelet: str, scheme: str = "fused") -> bool:
@@ -235,18 +259,23 @@ def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=
                polyconv=False, persistent=False, ws=None, fused=False):
     torch = _torch()
     _check(x)
-    x2 = x.reshape(-1, *x.shape[-2:]) if x.is_contiguous() else x.contiguous().reshape(-1, *x.shape[-2:])
+    if not x.is_contiguous():
+        x = x.contiguous()
     if out is None:
-        out = torch.empty_like(x2)
+        out = torch.empty_like(x)
     else:
         _check(out)
         if out.shape != x.shape or out.dtype != x.dtype or out.device != x.device:
             raise ValueError("out must match the input's shape, dtype and device")
         if not out.is_contiguous():
             raise ValueError("out must be contiguous")
-        out = out.reshape(x2.shape)
-    H, W = x2.shape[-2:]
-    planes = x2.shape[0]
+    result = out
+    H, W = x.shape[-2], x.shape[-1]
+    if x.dim() == 2:                      # one plane: no reshaped views (per-call host time)
+        x2, planes = x, 1
+    else:
+        x2, out = x.reshape(-1, H, W), out.reshape(-1, H, W)
+        planes = x2.shape[0]
     dt = dtype_code(x2)
     stream = _stream_ptr(x2)
     flags = ((DWT2_FLAG_SPLIT if split else 0) | (DWT2_FLAG_SEPARABLE if separable else 0)
@@ -256,23 +285,25 @@ def _transform(fn, name, x, wavelet, levels, split, out, config=None, separable=
         config = tuned_config(_DIRECTIONS[name], wavelet, dt, H, W, levels)
         scheme = ("split" if split else "separable" if separable else "factored" if factored
                   else "polyconv" if polyconv else "fused")
-        if config is not None and not config_supports(config, _DIRECTIONS[name], wavelet, scheme):
+        if config is not None and not _config_ok(config, _DIRECTIONS[name], wavelet, scheme):
             config = None                 # the library's default for this case
     if config is not None:
         flags |= DWT2_FLAG_KERNEL(config)
     # one call for all planes (at most 2^31 - 1 per call)
     step = (1 << 31) - 1
+    x_ptr, out_ptr, es = x2.data_ptr(), out.data_ptr(), x2.element_size()
+    xp, op = x2.stride(-2), out.stride(-2)                 # pitches
+    xs, os_ = (H * xp, H * op) if planes == 1 else (x2.stride(0), out.stride(0))
     for p0 in range(0, planes, step):
         n = min(step, planes - p0)
         w = ws if ws is not None else workspace(H, W, levels, dt, x2.device, n)
         ws_ptr = ctypes.c_void_p(w.data_ptr() if w is not None else 0)
         ws_n = w.numel() if w is not None else 0
-        st = fn(ctypes.c_void_p(x2[p0].data_ptr()), ctypes.c_void_p(out[p0].data_ptr()), n,
-                x2.stride(0), out.stride(0), H, W, x2.stride(-2), out.stride(-2), dt, WAVELETS[wavelet],
-                levels, DWT2_SYMMETRIC_WHOLE, flags, ws_ptr, ws_n, stream)
+        st = fn(ctypes.c_void_p(x_ptr + p0 * xs * es), ctypes.c_void_p(out_ptr + p0 * os_ * es), n, xs, os_,
+                H, W, xp, op, dt, WAVELETS[wavelet], levels, DWT2_SYMMETRIC_WHOLE, flags, ws_ptr, ws_n, stream)
         if st != DWT2_OK:
             raise DWT2Error(st, name)
-    return out.reshape(x.shape)
+    return result
 
 
 def fwd(x, wavelet: str = "cdf97", levels: int = 1, split: bool = False, out=None, config=None,

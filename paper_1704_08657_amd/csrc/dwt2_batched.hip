@@ -80,6 +80,27 @@ __device__ __forceinline__ void image_hw(const ImageSet& S, int i, int32_t* h, i
 // N values per thread at once: each wave scans with lane shuffles, the wave
 // totals meet in LDS; two barriers per call.  tot[k] receives the sum of
 // the k-th values over the work-group.
+// The last index i in [0, count) with a[i] <= t, for a non-decreasing a
+// with a[0] <= t (count and t uniform over the wave).  Every wave searches
+// on its own: a pass loads 64 evenly spaced entries of the current segment
+// (one per lane, one memory round trip) and keeps the segment after the
+// last sample <= t, so up to 64 entries take one pass and up to 4096 two,
+// where a binary search takes log2(count) dependent loads.
+__device__ __forceinline__ int last_at_most(const uint32_t* a, int count, uint32_t t) {
+    const int lane = threadIdx.x & (kLanes - 1);
+    int lo = 0, n = count;
+    while (n > 1) {
+        const int stride = (n + kLanes - 1) / kLanes;
+        const int k = lane * stride;
+        const bool ok = k < n && a[lo + k] <= t;
+        const unsigned long long m = __ballot(ok);     // a prefix of the lanes, lane 0 included
+        const int last = 63 - __builtin_clzll(m);
+        lo += last * stride;
+        n = min(stride, n - last * stride);
+    }
+    return lo;
+}
+
 template <int N, typename U>
 __device__ void block_scan(U (&v)[N], U (&tot)[N], U (*wsum)[kPlanThreads / kLanes]) {
     constexpr int kWaves = kPlanThreads / kLanes;
@@ -250,12 +271,7 @@ batched_level_kernel(const dwt2_image* imgs, int count, int levels, int l, unsig
     const uint32_t t = ((j / kLevelChunk) * 8 + (blockIdx.x & 7)) * kLevelChunk + j % kLevelChunk;
     if (t >= off[count]) return;                  // uniform over the work-group
     // image of tile t: off[] is strictly increasing (every image has a tile)
-    int lo = 0, hi = count;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[mid] <= t) lo = mid; else hi = mid;
-    }
-    const int i = lo;
+    const int i = last_at_most(off, count, t);
     const int tt = (int)(t - off[i]);
     const dwt2_image im = imgs[i];
 
@@ -382,12 +398,7 @@ persist_fwd_kernel(ImageSet S, int count, int levels, BatchLayout BL, uint64_t w
         const uint32_t p = sh_ticket[2];
         // the image of ticket p: the last image whose first ticket is <= p
         const uint32_t* q = qoff + ((size_t)l * kXcds + y) * (count + 1);
-        int lo = 0, hi = count;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (q[mid] <= p) lo = mid; else hi = mid;
-        }
-        const int i = lo;
+        const int i = last_at_most(q, count, p);
         const dwt2_image im = image_at(S, i, es);
         int32_t hl, wl, ntx, nty;
         level_size(im.height, im.width, l, &hl, &wl);

@@ -76,6 +76,19 @@ def test_batched_many_small_images(persistent):
 
 
 @pytest.mark.parametrize("persistent", [False, True])
+def test_batched_thousands_of_tiny_images(persistent):
+    # 5000 images of 8..40 pixels: finding a tile's image takes three passes
+    # of the 64-entry search (more than 4096 images), and every image is a
+    # single border tile
+    shapes, imgs = uneven(5000, 8, 40, seed=11, odd=True)
+    xs = [torch.from_numpy(x).to(dev()) for x in imgs]
+    lv = min(2, min(lifting.max_levels(*s) for s in shapes))
+    outs = checked(d.BatchedForward(xs, lv, persistent=persistent))
+    for x, y in zip(xs, outs):
+        assert torch.equal(y, d.fwd(x, "cdf97", lv))
+
+
+@pytest.mark.parametrize("persistent", [False, True])
 def test_batched_graph_replay(persistent):
     shapes, imgs = uneven(16, 64, 900, seed=5)
     xs = [torch.from_numpy(x).to(dev()) for x in imgs]
