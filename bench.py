@@ -99,16 +99,24 @@ def algorithmic_bytes(h, w, levels, elem):
     return total
 
 
-def time_steps(torch, fn, steps, warmup):
-    """Run warmup untimed steps, then time `steps` back-to-back steps.
+def time_steps(torch, fn, steps, warmup, warm_ms=0.0):
+    """Run warmup untimed steps (and more, until at least warm_ms of them
+    have run), then time `steps` back-to-back steps.
     Returns (total ms between the synchronisations, the steps' average ms
     from one HIP event pair around the whole timed region on the stream the
     kernels run on).  No event sits between the steps: an event pair per
     step costs several microseconds per step on this GPU."""
     stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
     for i in range(warmup):
         fn(i)
     torch.cuda.synchronize()
+    i = warmup
+    while (time.perf_counter() - t0) * 1e3 < warm_ms:
+        for _ in range(8):
+            fn(i)
+            i += 1
+        torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -293,7 +301,10 @@ def main():
                 return
             if tune_key is not None:
                 tune(name, *tune_key, levels, lambda c, i: fn(i, c))
-            _, ms = time_steps(torch, lambda i: fn(i, None), steps, 30)
+            # a form right after new buffers or an idle host phase reads up to
+            # 15% slow after 30 steps alone (the GPU is still raising its
+            # clocks): warm up for at least 25 ms as well
+            _, ms = time_steps(torch, lambda i: fn(i, None), steps, 30, warm_ms=25.0)
             ab = algorithmic_bytes(N, N, levels, elem)
             forms.append({"form": name, "Gpixel/s": round(px / (ms * 1e-3) / 1e9, 2),
                           "ms": round(ms, 4), "GB/s": round(ab / (ms * 1e-3) / 1e9, 1),
