@@ -1133,16 +1133,23 @@ __device__ __forceinline__ void load_tile(typename St<T>::V (&a)[K][Lay<BPL>::BX
 }
 
 // Whole-point symmetric extension of a sample index p into [0, n), n >= 2:
-// symmetric about both ends, hence periodic with period 2 (n - 1).  Reflected
-// about the nearer end until inside: one reflection for every index at most
-// n - 1 outside (all of a tile's halo once n > 8); each further pair of
-// reflections moves the index 2 (n - 1) closer, so tiny images take a few
-// more.  The loop is a handful of instructions where the period's modulo
-// (an integer division) is a few dozen at every inlined call site.
+// symmetric about both ends, hence periodic with period 2 (n - 1).  |p| is
+// folded into one period with a single-precision quotient (the hardware
+// reciprocal, within one unit in the last place, a multiply, a conversion)
+// and one correction either way: O(1) and a dozen instructions at each
+// inlined call site, where an integer modulo is a few dozen and reflecting
+// step by step takes about |p| / (n - 1) rounds (the lanes of a tile far
+// past a level of a few pixels).  The quotient is off by at most one
+// whenever |p| / (2 (n - 1)) < 2^21, which holds for every index a tile
+// reaches (at most a tile width past an image of at least 2 pixels).
 __device__ __forceinline__ int reflect(int p, int n) {
-    int q = p;
-    while (q < 0 || q >= n) q = q < 0 ? -q : 2 * (n - 1) - q;
-    return q;
+    if (p >= 0 && p < n) return p;
+    const int period = 2 * (n - 1);
+    int q = p < 0 ? -p : p;
+    q -= (int)((float)q * __builtin_amdgcn_rcpf((float)period)) * period;
+    if (q < 0) q += period;
+    else if (q >= period) q -= period;
+    return q < n ? q : period - q;
 }
 
 // Border tiles of the forward and inverse transforms: the tile is loaded
