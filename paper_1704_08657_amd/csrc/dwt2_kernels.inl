@@ -1541,17 +1541,23 @@ __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
 
 // The level parameters of plane `pl` of a plane batch (buffers offset by
 // the plane strides).
-// Branch-free: a buffer the direction does not use (null) may move by its
-// stride, and is never dereferenced.  Pointer arithmetic (not integer
-// casts) keeps the buffers in the global address space for the compiler, so
-// accesses stay global_load / global_store rather than flat ones.
+// Selects, not branches: a buffer the direction does not use stays null.
+// Pointer arithmetic (not integer casts) keeps the buffers in the global
+// address space for the compiler, so accesses stay global_load /
+// global_store rather than flat ones.
+template <typename T, typename P_>
+__device__ __forceinline__ P_* plane_ptr(P_* p, int pl, int64_t stride) {
+    return p ? static_cast<P_*>(static_cast<T*>(const_cast<void*>(static_cast<const void*>(p))) +
+                                (int64_t)pl * stride)
+             : p;
+}
 template <typename T>
 __device__ __forceinline__ LevelParams plane_params(const LevelParams& P, int pl) {
     LevelParams Q = P;
-    Q.in = static_cast<const T*>(P.in) + (int64_t)pl * P.in_ps;
-    Q.in_ll = static_cast<const T*>(P.in_ll) + (int64_t)pl * P.in_ll_ps;
-    Q.out = static_cast<T*>(P.out) + (int64_t)pl * P.out_ps;
-    Q.out_ll = static_cast<T*>(P.out_ll) + (int64_t)pl * P.out_ll_ps;
+    Q.in = plane_ptr<T>(P.in, pl, P.in_ps);
+    Q.in_ll = plane_ptr<T>(P.in_ll, pl, P.in_ll_ps);
+    Q.out = plane_ptr<T>(P.out, pl, P.out_ps);
+    Q.out_ll = plane_ptr<T>(P.out_ll, pl, P.out_ll_ps);
     return Q;
 }
 
