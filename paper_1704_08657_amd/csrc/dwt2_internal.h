@@ -102,6 +102,13 @@ struct LevelParams {
     // start 16-byte aligned, so 16-bit samples of 4 blocks per lane move as
     // one 16-byte access per row.
     int32_t vec16;
+    // CDF 9/7, a level whose output the call's next level reads (forward:
+    // the LL band of every level but the last; inverse / adjoint: the image
+    // of every level but the finest): interior tiles store it with ordinary
+    // stores, so the next level finds it in the caches; every other store
+    // stays nontemporal.  Read by the launcher, which picks the kernel
+    // variant.
+    int32_t ll_cached;
 };
 
 // Enqueue one level for `planes` planes (1 <= planes <= kMaxGridPlanes).

@@ -858,42 +858,47 @@ __device__ __forceinline__ void run(V (&a)[K][Lay<BPL>::BX], V (&e)[8], TileLds<
 // ---------------------------------------------------------------------------
 // Vector stores of whole output rows are streamed (nontemporal): the
 // outputs are not read again by this launch, and the stores of a tile cover
-// whole cache lines.
-template <typename T>
+// whole cache lines.  NT = false: an ordinary store, for an LL band that the
+// next level of the same transform reads at once.
+template <typename T, bool NT = true>
 __device__ __forceinline__ void nt_store2(T* p, T a, T b) {
     if constexpr (sizeof(T) == 4) {
         typedef int v2 __attribute__((ext_vector_type(2)));
         v2 q;
         q.x = __builtin_bit_cast(int, a);
         q.y = __builtin_bit_cast(int, b);
-        __builtin_nontemporal_store(q, reinterpret_cast<v2*>(p));
+        if constexpr (NT) __builtin_nontemporal_store(q, reinterpret_cast<v2*>(p));
+        else *reinterpret_cast<v2*>(p) = q;
     } else {
         typedef short v2 __attribute__((ext_vector_type(2)));
         v2 q;
         q.x = __builtin_bit_cast(short, a);
         q.y = __builtin_bit_cast(short, b);
-        __builtin_nontemporal_store(q, reinterpret_cast<v2*>(p));
+        if constexpr (NT) __builtin_nontemporal_store(q, reinterpret_cast<v2*>(p));
+        else *reinterpret_cast<v2*>(p) = q;
     }
 }
-template <typename T>
+template <typename T, bool NT = true>
 __device__ __forceinline__ void nt_store4(T* p, T a, T b, T c, T d) {
     if constexpr (sizeof(T) == 4) {
         typedef int v4 __attribute__((ext_vector_type(4)));
         v4 q;
         q.x = __builtin_bit_cast(int, a); q.y = __builtin_bit_cast(int, b);
         q.z = __builtin_bit_cast(int, c); q.w = __builtin_bit_cast(int, d);
-        __builtin_nontemporal_store(q, reinterpret_cast<v4*>(p));
+        if constexpr (NT) __builtin_nontemporal_store(q, reinterpret_cast<v4*>(p));
+        else *reinterpret_cast<v4*>(p) = q;
     } else {
         typedef short v4 __attribute__((ext_vector_type(4)));
         v4 q;
         q.x = __builtin_bit_cast(short, a); q.y = __builtin_bit_cast(short, b);
         q.z = __builtin_bit_cast(short, c); q.w = __builtin_bit_cast(short, d);
-        __builtin_nontemporal_store(q, reinterpret_cast<v4*>(p));
+        if constexpr (NT) __builtin_nontemporal_store(q, reinterpret_cast<v4*>(p));
+        else *reinterpret_cast<v4*>(p) = q;
     }
 }
 
-// Eight 16-bit samples as one 16-byte nontemporal store.
-template <typename T>
+// Eight 16-bit samples as one 16-byte nontemporal (NT) or ordinary store.
+template <typename T, bool NT = true>
 __device__ __forceinline__ void nt_store8(T* p, const T (&v)[8]) {
     static_assert(sizeof(T) == 2, "16-bit samples");
     typedef int v4 __attribute__((ext_vector_type(4)));
@@ -902,7 +907,8 @@ __device__ __forceinline__ void nt_store8(T* p, const T (&v)[8]) {
     q.y = (int)((unsigned)__builtin_bit_cast(unsigned short, v[2]) | ((unsigned)__builtin_bit_cast(unsigned short, v[3]) << 16));
     q.z = (int)((unsigned)__builtin_bit_cast(unsigned short, v[4]) | ((unsigned)__builtin_bit_cast(unsigned short, v[5]) << 16));
     q.w = (int)((unsigned)__builtin_bit_cast(unsigned short, v[6]) | ((unsigned)__builtin_bit_cast(unsigned short, v[7]) << 16));
-    __builtin_nontemporal_store(q, reinterpret_cast<v4*>(p));
+    if constexpr (NT) __builtin_nontemporal_store(q, reinterpret_cast<v4*>(p));
+    else *reinterpret_cast<v4*>(p) = q;
 }
 
 // Four consecutive samples of one image row starting at column c (a multiple
@@ -927,14 +933,14 @@ __device__ __forceinline__ void load4(const T* base, int64_t pitch, int row, int
     }
 }
 
-template <typename T, bool EDGE>
+template <typename T, bool EDGE, bool NT = true>
 __device__ __forceinline__ void store4(T* base, int64_t pitch, int row, int c, int h, int w, bool vec,
                                        typename St<T>::V v0, typename St<T>::V v1,
                                        typename St<T>::V v2, typename St<T>::V v3) {
     if (EDGE && (row >= h || c >= w)) return;
     T* p = base + (int64_t)row * pitch + c;
     if (vec && (!EDGE || c + 3 < w)) {
-        nt_store4(p, St<T>::store(v0), St<T>::store(v1), St<T>::store(v2), St<T>::store(v3));
+        nt_store4<T, NT>(p, St<T>::store(v0), St<T>::store(v1), St<T>::store(v2), St<T>::store(v3));
     } else {
         p[0] = St<T>::store(v0);
         if (!EDGE || c + 1 < w) p[1] = St<T>::store(v1);
@@ -1001,13 +1007,13 @@ __device__ __forceinline__ void loadN(const T* rowp, int gc, int ncols, bool row
     }
 }
 
-template <typename T, bool EDGE, int N>
+template <typename T, bool EDGE, int N, bool NT = true>
 __device__ __forceinline__ void storeN(T* rowp, int gc, int ncols, bool vec, const typename St<T>::V (&v)[N]) {
     if (EDGE && gc >= ncols) return;
     T* p = rowp + gc;
     if (vec && (!EDGE || gc + N - 1 < ncols)) {
-        if constexpr (N == 2) nt_store2(p, St<T>::store(v[0]), St<T>::store(v[1]));
-        else nt_store4(p, St<T>::store(v[0]), St<T>::store(v[1]), St<T>::store(v[2]), St<T>::store(v[3]));
+        if constexpr (N == 2) nt_store2<T, NT>(p, St<T>::store(v[0]), St<T>::store(v[1]));
+        else nt_store4<T, NT>(p, St<T>::store(v[0]), St<T>::store(v[1]), St<T>::store(v[2]), St<T>::store(v[3]));
     } else {
         p[0] = St<T>::store(v[0]);
 #pragma unroll
@@ -1256,7 +1262,7 @@ __device__ __forceinline__ void load_tile_mirror(typename St<T>::V (&a)[K][Lay<B
 // dropped.  Forward, interior tiles of 4-byte samples: one subband after the
 // other (the rows of LL, then HL, LH, HH), which suits the memory system
 // slightly better than interleaving the four quadrants row by row.
-template <int DIR, typename T, bool EDGE, int NW, int BPL, int K>
+template <int DIR, typename T, bool EDGE, int NW, int BPL, int K, bool LLC = false>
 __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::BX], const LevelParams& P,
                                            const Geo& g, int wv) {
     using V = typename St<T>::V;
@@ -1284,7 +1290,8 @@ __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::B
                            : k == 1 ? det + (int64_t)gr * P.out_pitch + g.nEc
                            : k == 2 ? det + (int64_t)(g.nEr + gr) * P.out_pitch
                                     : det + (int64_t)(g.nEr + gr) * P.out_pitch + g.nEc;
-                    storeN<T, EDGE, BPL>(row, g.gcL, (k & 1) ? g.nOc : g.nEc, vec, v);
+                    if (LLC && k == 0) storeN<T, EDGE, BPL, false>(row, g.gcL, g.nEc, vec, v);
+                    else storeN<T, EDGE, BPL>(row, g.gcL, (k & 1) ? g.nOc : g.nEc, vec, v);
                 }
             }
     } else {
@@ -1308,7 +1315,7 @@ __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::B
                             o[2 * j] = St<T>::store(a[r][4 * j + 2 * h]);
                             o[2 * j + 1] = St<T>::store(a[r][4 * j + 2 * h + 1]);
                         }
-                        nt_store8(img + (int64_t)(2 * gr + h) * P.out_pitch + 2 * g.gcL, o);
+                        nt_store8<T, !LLC>(img + (int64_t)(2 * gr + h) * P.out_pitch + 2 * g.gcL, o);
                     }
                     continue;
                 }
@@ -1317,8 +1324,8 @@ __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::B
             for (int q = 0; q < BPL / 2; ++q) {
                 const int c = 2 * g.gcL + 4 * q;
                 const V* b0 = &a[r][8 * q];
-                store4<T, EDGE>(img, P.out_pitch, 2 * gr, c, P.h, P.w, vec, b0[0], b0[1], b0[4], b0[5]);
-                store4<T, EDGE>(img, P.out_pitch, 2 * gr + 1, c, P.h, P.w, vec, b0[2], b0[3], b0[6], b0[7]);
+                store4<T, EDGE, !LLC>(img, P.out_pitch, 2 * gr, c, P.h, P.w, vec, b0[0], b0[1], b0[4], b0[5]);
+                store4<T, EDGE, !LLC>(img, P.out_pitch, 2 * gr + 1, c, P.h, P.w, vec, b0[2], b0[3], b0[6], b0[7]);
             }
         }
     }
@@ -1487,7 +1494,7 @@ __device__ __forceinline__ void store_tile_semi(typename St<T>::V (&a)[K][Lay<BP
 // belongs to the calling work-group.
 // SEMI: interior tiles of images with 8-byte aligned rows (vec8) take the
 // semi-vector path instead of the border path.
-template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL, bool SEMI = false>
+template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL, bool SEMI = false, bool LLC = false>
 __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
                                           TileLds<typename St<T>::V, NW, BPL, K>& lds, int lane, int wv) {
     using V = typename St<T>::V;
@@ -1523,7 +1530,7 @@ __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
         } else {
             load_tile<DIR, T, false, BPL>(a, e, P, g, tg, lane);
             run<DIR, WAV, false, SCH, NW, BPL>(a, e, lds, lane, wv, g, tg);
-            store_tile<DIR, T, false, NW, BPL>(a, P, g, wv);
+            store_tile<DIR, T, false, NW, BPL, K, LLC>(a, P, g, wv);
         }
     } else if constexpr (DIR != kAdjoint) {
         // border tile: symmetric extension at load time, unclamped steps
@@ -1573,7 +1580,7 @@ __device__ __forceinline__ void fetch_params(const LevelParams& P) {
                  "s"(P.vec16));
 }
 
-template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL, bool SEMI>
+template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL, bool SEMI, bool LLC = false>
 __global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
     using V = typename St<T>::V;
     __shared__ TileLds<V, NW, BPL, K> lds;
@@ -1597,7 +1604,7 @@ __global__ void __launch_bounds__(NW * kLanes) level_kernel(LevelParams P) {
     const int t = g - pl * nt;
     const int ty = t / P.tiles_x;
     const int tx = t - ty * P.tiles_x;
-    tile_body<DIR, WAV, T, SCH, NW, K, BPL, SEMI>(plane_params<T>(P, pl), tx, ty, lds, lane, wv);
+    tile_body<DIR, WAV, T, SCH, NW, K, BPL, SEMI, LLC>(plane_params<T>(P, pl), tx, ty, lds, lane, wv);
 }
 
 // ===========================================================================

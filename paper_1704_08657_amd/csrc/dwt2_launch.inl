@@ -5,7 +5,7 @@
 namespace dwt2 {
 namespace kern {
 
-template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL, bool SEMI>
+template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL, bool SEMI, bool LLC = false>
 hipError_t launch_grid(const LevelParams& p, int planes, hipStream_t s) {
     // the tiles of all planes, rounded up to a multiple of 8 chunks of
     // kRemapRows tile rows (see level_kernel); planes beyond what one grid
@@ -25,7 +25,7 @@ hipError_t launch_grid(const LevelParams& p, int planes, hipStream_t s) {
             if (q.out_ll) q.out_ll = static_cast<T*>(q.out_ll) + p0 * q.out_ll_ps;
         }
         const int64_t grid = (nt * q.planes + 8 * chunk - 1) / (8 * chunk) * (8 * chunk);
-        hipLaunchKernelGGL((level_kernel<DIR, WAV, T, SCH, NW, K, BPL, SEMI>), dim3((unsigned)grid),
+        hipLaunchKernelGGL((level_kernel<DIR, WAV, T, SCH, NW, K, BPL, SEMI, LLC>), dim3((unsigned)grid),
                            dim3(NW * kLanes), 0, s, q);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -34,11 +34,16 @@ hipError_t launch_grid(const LevelParams& p, int planes, hipStream_t s) {
 }
 
 // An image whose rows are 8-byte but not vector aligned runs its interior
-// tiles on the semi-vector path (fused and split schemes).
+// tiles on the semi-vector path (fused and split schemes).  A CDF 9/7 level
+// whose output the next level of the call reads stores it with ordinary
+// stores on the vector path (ll_cached).
 template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL>
 hipError_t launch_shape(const LevelParams& p, int planes, hipStream_t s) {
     if constexpr (SCH == kSchemeFused || SCH == kSchemeSplit) {
         if (!p.vec && p.vec8) return launch_grid<DIR, WAV, T, SCH, NW, K, BPL, true>(p, planes, s);
+    }
+    if constexpr (WAV == kCdf97) {
+        if (p.ll_cached && p.vec) return launch_grid<DIR, WAV, T, SCH, NW, K, BPL, false, true>(p, planes, s);
     }
     return launch_grid<DIR, WAV, T, SCH, NW, K, BPL, false>(p, planes, s);
 }
