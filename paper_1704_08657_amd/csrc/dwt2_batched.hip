@@ -23,10 +23,13 @@
 // last ones of level l are still running.
 //
 // Ordering across work-groups, possibly on different XCDs (agent scope):
-//   publish: every thread fences (release, agent: its stores reach the
-//            point of coherence for the whole device), the work-group
-//            synchronises, thread 0 increments the chunk counter (atomic,
-//            release, agent);
+//   publish: the only data a later tile reads is the LL band of a level
+//            below the last, and a tile stores it with agent-scope stores,
+//            which the L2 writes through to the point of coherence for the
+//            whole device; every wave waits until its stores have
+//            completed, the work-group synchronises, thread 0 increments
+//            the chunk counter (atomic, agent).  A release fence instead
+//            would write back the XCD's whole L2 for every tile;
 //   wait:    thread 0 polls the counters (atomic loads, agent scope), the
 //            work-group synchronises, every thread fences (acquire, agent:
 //            stale cached lines are invalidated) before it loads.
@@ -452,14 +455,25 @@ persist_fwd_kernel(ImageSet S, int count, int levels, BatchLayout BL, uint64_t w
         // tiles (fused and split steps, as the level kernel)
         bool semi = false;
         if constexpr (SCH == kSchemeFused || SCH == kSchemeSplit) semi = !P.vec && P.vec8;
-        if (semi) tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, true>(P, tcol, trow, lds, lane, wv);
-        else tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, false>(P, tcol, trow, lds, lane, wv);
+        // a level that a later one reads stores its LL band with agent-scope
+        // stores (written through the L2, see coherent_store)
+        const bool read_later = l + 1 < levels;
+        if (semi) {
+            if (read_later) tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, true, false, true>(P, tcol, trow, lds, lane, wv);
+            else tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, true>(P, tcol, trow, lds, lane, wv);
+        } else {
+            if (read_later) tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, false, false, true>(P, tcol, trow, lds, lane, wv);
+            else tile_body<kForward, kCdf97, T, SCH, NW, K, BPL, false>(P, tcol, trow, lds, lane, wv);
+        }
 
-        // publish the tile: every thread's stores, then the chunk counter
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // publish the tile: every wave waits until its stores have completed
+        // (the LL band's agent-scope stores are then where every XCD reads
+        // them), then thread 0 adds the tile to the chunk counter.  No L2
+        // writeback: the band never sits dirty in this XCD's L2.
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(done + cbase[l] + g0 + chunk, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(done + cbase[l] + g0 + chunk, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

@@ -911,6 +911,21 @@ __device__ __forceinline__ void nt_store8(T* p, const T (&v)[8]) {
     else *reinterpret_cast<v4*>(p) = q;
 }
 
+// One LL sample that a later level of the same persistent launch reads,
+// possibly on another XCD: an agent-scope store, which the L2 writes
+// through, so the reader sees it after its acquire (an L2 invalidate)
+// without the writing tile having to write back its whole L2.
+template <typename T>
+__device__ __forceinline__ void coherent_store(T* p, typename St<T>::V v) {
+    const T t = St<T>::store(v);
+    if constexpr (sizeof(T) == 4)
+        __hip_atomic_store(reinterpret_cast<uint32_t*>(p), __builtin_bit_cast(uint32_t, t), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    else
+        __hip_atomic_store(reinterpret_cast<uint16_t*>(p), __builtin_bit_cast(uint16_t, t), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Four consecutive samples of one image row starting at column c (a multiple
 // of 4); samples outside [0, w) or rows outside [0, h) read as 0.
 template <typename T, bool EDGE>
@@ -1262,7 +1277,7 @@ __device__ __forceinline__ void load_tile_mirror(typename St<T>::V (&a)[K][Lay<B
 // dropped.  Forward, interior tiles of 4-byte samples: one subband after the
 // other (the rows of LL, then HL, LH, HH), which suits the memory system
 // slightly better than interleaving the four quadrants row by row.
-template <int DIR, typename T, bool EDGE, int NW, int BPL, int K, bool LLC = false>
+template <int DIR, typename T, bool EDGE, int NW, int BPL, int K, bool LLC = false, bool LLX = false>
 __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::BX], const LevelParams& P,
                                            const Geo& g, int wv) {
     using V = typename St<T>::V;
@@ -1290,8 +1305,15 @@ __device__ __forceinline__ void store_tile(typename St<T>::V (&a)[K][Lay<BPL>::B
                            : k == 1 ? det + (int64_t)gr * P.out_pitch + g.nEc
                            : k == 2 ? det + (int64_t)(g.nEr + gr) * P.out_pitch
                                     : det + (int64_t)(g.nEr + gr) * P.out_pitch + g.nEc;
-                    if (LLC && k == 0) storeN<T, EDGE, BPL, false>(row, g.gcL, g.nEc, vec, v);
-                    else storeN<T, EDGE, BPL>(row, g.gcL, (k & 1) ? g.nOc : g.nEc, vec, v);
+                    if (LLX && k == 0) {
+#pragma unroll
+                        for (int b = 0; b < BPL; ++b)
+                            if (!EDGE || g.gcL + b < g.nEc) coherent_store<T>(row + g.gcL + b, v[b]);
+                    } else if (LLC && k == 0) {
+                        storeN<T, EDGE, BPL, false>(row, g.gcL, g.nEc, vec, v);
+                    } else {
+                        storeN<T, EDGE, BPL>(row, g.gcL, (k & 1) ? g.nOc : g.nEc, vec, v);
+                    }
                 }
             }
     } else {
@@ -1438,7 +1460,7 @@ __device__ __forceinline__ void load_tile_semi(typename St<T>::V (&a)[K][Lay<BPL
     }
 }
 
-template <int DIR, typename T, int NW, int BPL, int K>
+template <int DIR, typename T, int NW, int BPL, int K, bool LLX = false>
 __device__ __forceinline__ void store_tile_semi(typename St<T>::V (&a)[K][Lay<BPL>::BX], const LevelParams& P,
                                                 const Geo& g, int wv, int lane) {
     using V = typename St<T>::V;
@@ -1464,8 +1486,14 @@ __device__ __forceinline__ void store_tile_semi(typename St<T>::V (&a)[K][Lay<BP
                            : k == 1 ? det + (int64_t)gr * P.out_pitch + g.nEc
                            : k == 2 ? det + (int64_t)(g.nEr + gr) * P.out_pitch
                                     : det + (int64_t)(g.nEr + gr) * P.out_pitch + g.nEc;
-                    if ((k & 1) && !hi_pairs) storeN_shifted<T, BPL>(row + g.gcL, v, lane);
-                    else storeN_pairs<T, BPL>(row + g.gcL, v);
+                    if (LLX && k == 0) {
+#pragma unroll
+                        for (int b = 0; b < BPL; ++b) coherent_store<T>(row + g.gcL + b, v[b]);
+                    } else if ((k & 1) && !hi_pairs) {
+                        storeN_shifted<T, BPL>(row + g.gcL, v, lane);
+                    } else {
+                        storeN_pairs<T, BPL>(row + g.gcL, v);
+                    }
                 }
             }
     } else {
@@ -1494,7 +1522,8 @@ __device__ __forceinline__ void store_tile_semi(typename St<T>::V (&a)[K][Lay<BP
 // belongs to the calling work-group.
 // SEMI: interior tiles of images with 8-byte aligned rows (vec8) take the
 // semi-vector path instead of the border path.
-template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL, bool SEMI = false, bool LLC = false>
+template <int DIR, int WAV, typename T, int SCH, int NW, int K, int BPL, bool SEMI = false, bool LLC = false,
+          bool LLX = false>
 __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
                                           TileLds<typename St<T>::V, NW, BPL, K>& lds, int lane, int wv) {
     using V = typename St<T>::V;
@@ -1526,18 +1555,18 @@ __device__ __forceinline__ void tile_body(const LevelParams& P, int tx, int ty,
         if constexpr (SEMI) {
             load_tile_semi<DIR, T, BPL>(a, e, P, g, tg, lane);
             run<DIR, WAV, false, SCH, NW, BPL>(a, e, lds, lane, wv, g, tg);
-            store_tile_semi<DIR, T, NW, BPL>(a, P, g, wv, lane);
+            store_tile_semi<DIR, T, NW, BPL, K, LLX>(a, P, g, wv, lane);
         } else {
             load_tile<DIR, T, false, BPL>(a, e, P, g, tg, lane);
             run<DIR, WAV, false, SCH, NW, BPL>(a, e, lds, lane, wv, g, tg);
-            store_tile<DIR, T, false, NW, BPL, K, LLC>(a, P, g, wv);
+            store_tile<DIR, T, false, NW, BPL, K, LLC, LLX>(a, P, g, wv);
         }
     } else if constexpr (DIR != kAdjoint) {
         // border tile: symmetric extension at load time, unclamped steps
         // (the split applies to interior tiles only)
         load_tile_mirror<DIR, T, BPL>(a, e, P, g, tg, lane);
         run<DIR, WAV, false, SCH == kSchemeSplit ? kSchemeFused : SCH, NW, BPL>(a, e, lds, lane, wv, g, tg);
-        store_tile<DIR, T, true, NW, BPL>(a, P, g, wv);
+        store_tile<DIR, T, true, NW, BPL, K, false, LLX>(a, P, g, wv);
     } else {
         // the adjoint's border weights are not a symmetric extension
         load_tile<DIR, T, true, BPL>(a, e, P, g, tg, lane);
