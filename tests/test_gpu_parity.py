@@ -445,6 +445,26 @@ def test_semi_vector_path_inverse_adjoint_bit_identical(shape):
         assert rel_err(host(r), lifting.inv(c, "cdf97", 3)) <= TOL97, cfg
 
 
+@pytest.mark.parametrize("tdt", [torch.float32, torch.bfloat16])
+def test_two_levels_equal_two_single_level_calls(tdt):
+    # 8192^2: level 1's LL band (64 MiB FP32, 32 MiB BF16) and, for the
+    # inverse, level 2's image take the variant that stores them with
+    # ordinary stores for the next level; every single-level call stores
+    # nontemporally.  Same values either way: a two-level call equals two
+    # one-level calls bit for bit, forward and inverse.
+    n, h = 8192, 4096
+    say("two levels vs two single-level calls", tdt)
+    x = gpu(workloads.uniform(n, n, seed=4), tdt)
+    two = d.fwd(x, "cdf97", 2, config=3)
+    one = d.fwd(x, "cdf97", 1, config=3)
+    one[:h, :h] = d.fwd(one[:h, :h].contiguous(), "cdf97", 1, config=3)
+    assert torch.equal(two, one)
+    back = d.inv(two, "cdf97", 2, config=3)
+    c1 = two.clone()
+    c1[:h, :h] = d.inv(two[:h, :h].contiguous(), "cdf97", 1, config=3)
+    assert torch.equal(back, d.inv(c1, "cdf97", 1, config=3))
+
+
 def test_multilevel_graph_replay():
     """A 5-level forward + inverse of a plane stack (one launch per level,
     workspace from the graph's pool) captured in a graph and replayed with
