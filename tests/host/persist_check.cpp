@@ -2,7 +2,8 @@
 // library's plan header (dwt2_batch_plan.h): the planner's tables computed
 // as the planner kernel computes them, then one thread per work-group
 // running the persistent kernel's loop (ticket from the lowest level with
-// tickets, own sub-queue first; binary search of the image; tile of the
+// tickets, own sub-queue first; the image of the ticket, by bisection here,
+// which finds the same image as the kernel's 64-way search; tile of the
 // ticket; wait for the chunks of the previous level; publish).  The
 // "computation" of a tile checks, by brute force and independently of
 // dep_chunks, that every tile of the previous level whose LL rows the tile
